@@ -1,0 +1,274 @@
+/*
+ * cprand.h -- C ABI of a gfx950 (MI355X) library for randomized CP-ALS:
+ * CPRAND and CPRAND-MIX of Battaglino, Ballard and Kolda, "A Practical
+ * Randomized CP Tensor Decomposition" (SIAM J. Matrix Anal. Appl., 2018).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Indices are 0-based (the paper is 1-based).  Modes are 0 .. order-1.
+ *  - A tensor is a device buffer described by cprand_tensor: dims and
+ *    per-mode strides in elements.  The usual layout is column-major (mode 0
+ *    fastest), the element order of the unfolding map of Section 2.1; any
+ *    strides are accepted by the calls that gather fibers, so a copy with
+ *    mode n innermost (cprand_layout_copy) serves mode-n steps.
+ *  - Factor matrices A^(m) are row-major I_m x R device buffers (the R
+ *    entries of a row are contiguous).  Their element type is the "real
+ *    type" of the tensor: double for F64/C128 tensors, float for F32, C64
+ *    and BF16 tensors.  Mixed (complex) factors are interleaved (re, im)
+ *    pairs of that real type.
+ *  - Every pointer named "device" must point to memory the GPU can read or
+ *    write; "host" pointers are read on the calling thread before the call
+ *    returns.  The caller owns every buffer; the library never frees or
+ *    retains caller memory.  Scratch memory comes from a caller-provided
+ *    workspace whose size cprand_workspace_size() returns (the plan API
+ *    allocates its own).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *    and is stream-ordered; calls return once the work is enqueued, without
+ *    synchronising, except where stated.
+ *  - Return value: 0 on success, a negative CPRAND_E* code on error (outputs
+ *    then unspecified; cprand_last_error() holds a message).  Argument
+ *    validation happens before any HIP call.
+ */
+#ifndef CPRAND_H
+#define CPRAND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPRAND_MAX_ORDER 8
+#define CPRAND_MAX_RANK 64
+
+/* status codes */
+#define CPRAND_OK 0
+#define CPRAND_W_PINV 1          /* a normal matrix was not positive definite: pseudo-inverse used */
+#define CPRAND_W_MAXIT 2         /* the iteration cap ended the run */
+#define CPRAND_W_FALLBACK 4      /* the learned proposal fell back to mixture/uniform sampling */
+#define CPRAND_EINVAL (-1)
+#define CPRAND_ENAN (-2)
+#define CPRAND_EHIP (-3)
+#define CPRAND_ENOMEM (-4)
+#define CPRAND_EUNSUPPORTED (-5)
+
+/* element types */
+#define CPRAND_F64 0
+#define CPRAND_F32 1
+#define CPRAND_BF16 2
+#define CPRAND_C64 3   /* complex float, interleaved */
+#define CPRAND_C128 4  /* complex double, interleaved */
+
+typedef struct cprand_tensor {
+    int32_t order;                       /* 2 .. CPRAND_MAX_ORDER */
+    int32_t dtype;                       /* CPRAND_F64 .. CPRAND_C128 */
+    int64_t dims[CPRAND_MAX_ORDER];      /* I_m >= 1 */
+    int64_t strides[CPRAND_MAX_ORDER];   /* in elements, >= 1 */
+    void *data;                          /* device */
+} cprand_tensor;
+
+/* ---------------------------------------------------------------------------
+ * Version, errors, workspace.
+ */
+const char *cprand_version(void);
+const char *cprand_strerror(int status);
+/* Message of the last failing call on this thread ("" if none). */
+const char *cprand_last_error(void);
+
+/* Bytes of workspace that cprand_mttkrp_sampled, cprand_solve,
+ * cprand_fit_est, cprand_norm and cprand_mix need for a tensor X (its dims),
+ * rank R, S samples and P_hat fit entries.  0 on invalid arguments. */
+size_t cprand_workspace_size(const cprand_tensor *X, int32_t R, int32_t S, int32_t P_hat);
+
+/* ---------------------------------------------------------------------------
+ * Sampling (Section 3.2; Alg. 3 "define sampling operator").
+ *
+ * Draws S multi-indices over the modes other than n, independently and with
+ * replacement.  Sample s of outer iteration t uses Philox4x64-10 with key
+ * (seed, 5) and counter (s, t, n, b); the k-th mode other than n takes word
+ * k % 4 of block b = k / 4.  Uniform sampling maps a word u to
+ * floor(u * I_m / 2^64).  With cdf != NULL, cdf[m] (device, I_m + 1 uint64
+ * values, cdf[m][0] = 0, strictly increasing) is the integer proposal table
+ * of mode m: the row drawn is the first i with cdf[m][i+1] > floor(u * Q /
+ * 2^64), Q = cdf[m][I_m]; w[s] = prod_m Q_m / (I_m q_i) (FP64, modes in
+ * increasing order) is the importance weight (1 for uniform sampling).
+ *
+ *   dims  host, `order` entries        cdf   host array of `order` device
+ *   idx   device, S x order int32,           pointers (entry n ignored), or NULL
+ *         row-major, column n = -1     w     device, S doubles, or NULL
+ */
+int cprand_sample(int32_t order, const int64_t *dims, int32_t n, int32_t S,
+                  uint64_t seed, uint64_t t, const uint64_t *const *cdf,
+                  int32_t *idx, double *w, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Sampled MTTKRP and Gram (Alg. 2 and Alg. 3; for mixed tensors Alg. 4 and
+ * eq. rcLS).
+ *
+ * With Z_S the sampled Khatri-Rao rows (row s = Hadamard product of rows
+ * idx[s, m] of A^(m), m != n) and X_S the I_n x S sampled mode-n fibers:
+ *   W = X_S diag(w) Z_S   (I_n x R, row-major, real type of X)
+ *   V = Z_S^T diag(w) Z_S (R x R, row-major, FP64)
+ * For a mixed tensor (dtype C64/C128) A holds the mixed factors, the fibers
+ * are unmixed in mode n by D_n F_n^* (unmix_signs = D_n, device int8, I_n
+ * entries of +-1) and W, V are the normal-equation blocks of the stacked
+ * real problem: W = Re(M) Re(Z) + Im(M) Im(Z), V = Re(Z^H Z) with M the
+ * unmixed fibers.  For BF16 tensors the fibers and Z_S enter the product in
+ * BF16 with FP32 accumulation; W is then float.
+ *
+ *   A     host array of `order` device pointers (entry n ignored)
+ *   idx   device S x order int32 from cprand_sample
+ *   w     device S doubles or NULL (all ones)
+ *   W, V  device outputs
+ */
+int cprand_mttkrp_sampled(const cprand_tensor *X, int32_t n, const void *const *A,
+                          int32_t R, int32_t S, const int32_t *idx, const double *w,
+                          const int8_t *unmix_signs, void *W, double *V,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Least-squares solve and normalisation (Alg. 3 solve and normalise steps).
+ *
+ * A = W V^{-1} by an FP64 Cholesky factorisation of V; if V is not
+ * numerically positive definite, by its pseudo-inverse (cyclic Jacobi
+ * eigen-decomposition, eigenvalues below 1e-12 of the largest dropped) and
+ * *info = CPRAND_W_PINV.  With W_refine != NULL (float, I_n x R, the MTTKRP
+ * of the same samples from FP32 data) one refinement step follows:
+ * A += (W_refine - A V) V^{-1}.  The columns of A are then scaled to unit
+ * 2-norm and lambda_out receives the norms (a zero column stays zero with
+ * lambda 0).
+ *
+ *   V        device R x R FP64          dtype   CPRAND_F64 or CPRAND_F32, the
+ *   W        device I_n x R row-major            type of W and A_out
+ *   A_out    device I_n x R row-major   info    device int32 or NULL
+ *   lambda_out device R doubles
+ */
+int cprand_solve(int32_t I_n, int32_t R, const double *V, const void *W, int32_t dtype,
+                 const float *W_refine, void *A_out, double *lambda_out, int32_t *info,
+                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Sampled fit estimate (Section 3.4).
+ *
+ * Draws P_hat multi-indices once per seed (Philox key (seed, 6), counter
+ * (p, 0, 0, b), mode k from word k % 4 of block k / 4) and writes
+ *   *fit_out = 1 - sqrt(P * mean_p |x_p - model_p|^2) / normX,
+ * model_p = sum_r lambda_r prod_m A^(m)(i_m, r), P = prod I_m; all sums in
+ * FP64.  For a mixed tensor pass the mixed factors: the estimate is then of
+ * the mixed residual, whose norm equals the unmixed one.
+ *
+ *   normX   device scalar (||X||)     fit_out  device scalar
+ *   A       host array of `order` device pointers; lambda device R doubles
+ */
+int cprand_fit_est(const cprand_tensor *X, const double *normX, const void *const *A,
+                   const double *lambda, int32_t R, int32_t P_hat, uint64_t seed,
+                   double *fit_out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ||X|| (Frobenius, FP64 sums over all elements) into device *normX_out. */
+int cprand_norm(const cprand_tensor *X, double *normX_out, void *workspace,
+                size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Mixing (Section 2.2 and Section 3.3, Alg. 4).
+ *
+ * signs: D_m entry i is -1 when bit 63 of word 0 of Philox4x64-10 with key
+ * (seed, 3) and counter (i, m, 0, 0) is set, else +1; written to `signs`
+ * (device int8, sum I_m entries, mode 0 first).
+ * Xhat = X x_0 F_0 D_0 ... x_{N-1} F_{N-1} D_{N-1}, F_m the unitary DFT
+ * (scaled by 1/sqrt(I_m)).  X is real (F32 or F64, any strides); Xhat is a
+ * caller-allocated complex tensor (C64 for F32 input, C128 for F64) with
+ * column-major strides.  ||X|| is written to device *normX_out.  Every I_m
+ * must factor into 2, 3, 5 and 7.
+ */
+int cprand_mix(const cprand_tensor *X, uint64_t seed, const cprand_tensor *Xhat,
+               int8_t *signs, double *normX_out, void *workspace, size_t workspace_bytes,
+               void *stream);
+
+/* A-hat = F D A for one I x R row-major real factor (dtype F32 or F64) into
+ * the complex row-major Ahat; with inverse != 0, A = Re(D F^* A-hat) instead
+ * (A complex input, Ahat real output). */
+int cprand_mix_factor(int32_t I, int32_t R, const void *A, int32_t dtype,
+                      const int8_t *signs, void *Ahat, int32_t inverse, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Layout: a copy of X with mode n innermost (its mode-n fibers contiguous,
+ * each padded to ld elements), optionally converted to BF16 (round to
+ * nearest even) or between real types.  Y->dims must equal X->dims;
+ * Y->strides must be the ones cprand_mode_major_strides() returns for
+ * (dims, n, ld).  A one-time pass that makes fiber gathers contiguous. */
+int cprand_mode_major_strides(int32_t order, const int64_t *dims, int32_t n, int64_t ld,
+                              int64_t *strides_out);
+int cprand_layout_copy(const cprand_tensor *X, int32_t n, const cprand_tensor *Y,
+                       void *stream);
+
+/* ---------------------------------------------------------------------------
+ * The whole decomposition (Alg. 3 / Alg. 4 with the stopping rules of
+ * Section 3.4 and Section 4.2).
+ */
+#define CPRAND_MIX_NONE 0
+#define CPRAND_MIX_FFT 1
+
+#define CPRAND_PREC_NATIVE 0       /* arithmetic in the tensor's own type (F64 or F32) */
+#define CPRAND_PREC_BF16_REFINE 1  /* BF16 products, FP32 refinement, FP64 solve */
+
+#define CPRAND_PROPOSAL_UNIFORM 0
+#define CPRAND_PROPOSAL_TABLE 1    /* caller-provided integer proposals, fixed */
+#define CPRAND_PROPOSAL_LEARNED 2  /* MLP proposal recomputed each mode step */
+
+typedef struct cprand_opts {
+    int32_t R;            /* rank, 1 .. CPRAND_MAX_RANK */
+    int32_t S;            /* samples per least-squares solve */
+    int32_t P_hat;        /* entries of the fit estimate */
+    int32_t max_iters;    /* outer iterations at most */
+    uint64_t seed;
+    double tol;           /* stop when |F_t - F_{t-1}| <= tol (0 = off) */
+    double fit_target;    /* stop when F_t >= fit_target (> 1 = off) */
+    int32_t patience;     /* stop when the best F has not improved for this many iterations (0 = off) */
+    int32_t mix;          /* CPRAND_MIX_* */
+    int32_t precision;    /* CPRAND_PREC_* */
+    int32_t proposal;     /* CPRAND_PROPOSAL_* */
+    int32_t layout;       /* 0 = mode-major copies where fibers are strided or misaligned, 1 = never copy */
+    int32_t use_graph;    /* 1 = replay each outer iteration as a HIP graph */
+    double alpha;         /* uniform share of importance proposals */
+    const uint64_t *const *proposal_cdf; /* PROPOSAL_TABLE: host array of `order` device CDFs */
+    const float *mlp_params;            /* PROPOSAL_LEARNED: device, cprand_mlp_param_count() floats */
+} cprand_opts;
+
+typedef struct cprand_report {
+    int32_t iters;          /* outer iterations run */
+    int32_t flags;          /* OR of CPRAND_W_* warnings */
+    double fit_est;         /* last sampled fit estimate */
+    double setup_ms;        /* norm / mixing / layout copies / conversions */
+    double loop_ms;         /* the ALS loop */
+    double *fit_history;    /* host, max_iters entries, or NULL */
+    int32_t *proposal_history; /* host, max_iters entries (proposal in use), or NULL */
+    double norm_ms;                      /* ||X|| pass (HIP events) */
+    double mix_ms[CPRAND_MAX_ORDER];     /* mixing pass along each mode, 0 when not mixed */
+    double layout_ms[CPRAND_MAX_ORDER];  /* mode-major copy for each mode, 0 when none */
+} cprand_report;
+
+typedef struct cprand_plan cprand_plan;
+
+/* Allocate the device buffers for decomposing tensors shaped like X under
+ * opts (X->data is not read).  X: F64 or F32, any strides. */
+int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_plan **plan);
+/* Decompose X (same shape and strides as at creation).  A_inout: host array
+ * of `order` device pointers to row-major I_m x R factors of the real type;
+ * A^(1..N-1) on entry are the initial factors (A^(0) is not read); on return
+ * all hold the final unit-column factors and lambda_out (device, R doubles)
+ * the weights.  Synchronises `stream` once per outer iteration to read the
+ * fit estimate.  Returns 0 or a warning bit set, or a negative error. */
+int cprand_plan_run(cprand_plan *plan, const cprand_tensor *X, void *const *A_inout,
+                    double *lambda_out, cprand_report *report, void *stream);
+void cprand_plan_destroy(cprand_plan *plan);
+
+/* cprand_plan_create + cprand_plan_run + cprand_plan_destroy. */
+int cprand_als(const cprand_tensor *X, const cprand_opts *opts, void *const *A_inout,
+               double *lambda_out, cprand_report *report, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPRAND_H */

@@ -1,0 +1,614 @@
+// The whole decomposition: CPRAND (Alg. 3) and CPRAND-MIX (Alg. 4) with the
+// sampled fit estimate and the stopping rules of Section 3.4 / Section 4.2,
+// plus the BF16 precision form.  A plan owns every device buffer, so a run
+// allocates nothing; each outer iteration is a fixed kernel sequence
+// (optionally replayed as a HIP graph) whose only host synchronisation is
+// the 8-byte read of the fit estimate that the stopping rule needs.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "api_internal.hpp"
+
+namespace cprand {
+
+int mix_tensor_impl(const cprand_tensor *X, const cprand_tensor *Xhat, uint64_t seed, int8_t *signs,
+                    double *normX_out, void *workspace, size_t workspace_bytes, hipStream_t st) {
+    if (!workspace || workspace_bytes < 4096 * 8)
+        return set_error(CPRAND_EINVAL, "workspace of 32768 bytes needed");
+    const int xk = kind_of(X->dtype);
+    const bool dbl = kind_of(Xhat->dtype) == K_C128;
+    const ModeInfo mi = mode_info(X, 0);
+    hipError_t e = launch_signs(mi, seed, signs, st);
+    if (e != hipSuccess) return hip_fail(e, "sign kernel");
+    int32_t np = 0;
+    e = launch_normsq_partial(mi, X->data, xk, (double *)workspace, &np, st);
+    if (e == hipSuccess) e = launch_sqrt_sum((double *)workspace, np, normX_out, st);
+    if (e != hipSuccess) return hip_fail(e, "norm kernels");
+    for (int m = 0; m < X->order; ++m) {
+        FftPlan *fp = fft_plan_get(X->dims[m], dbl, &e);
+        if (!fp) return set_error(CPRAND_EUNSUPPORTED, "mode %d length %lld does not factor into 2,3,5,7", m,
+                                  (long long)X->dims[m]);
+        e = launch_mix_pass(fp, dbl, mi, X->data, xk, Xhat->data, m, m == 0, signs, nullptr, nullptr, st);
+        if (e != hipSuccess) return hip_fail(e, "mix pass");
+    }
+    return CPRAND_OK;
+}
+
+}  // namespace cprand
+
+using namespace cprand;
+
+struct View {
+    void *data = nullptr;   // NULL: the caller's X (or the plan's X-hat) at run time
+    bool own = false;
+    bool from_xhat = false;
+    int kind = 0;
+    int64_t strides[CPRAND_MAX_ORDER] = {};
+    int64_t ld = 0;
+};
+
+struct cprand_plan {
+    cprand_opts o{};
+    int N = 0;
+    int64_t dims[CPRAND_MAX_ORDER] = {};
+    int64_t xstrides[CPRAND_MAX_ORDER] = {};
+    int xkind = 0;
+    int64_t P = 1;
+    bool dbl = false, mix = false, bf16 = false, refine = false;
+    int gkind = 0;
+    View gview[CPRAND_MAX_ORDER], rview[CPRAND_MAX_ORDER];
+    void *xhat = nullptr;
+    int8_t *signs = nullptr;
+    void *fac[CPRAND_MAX_ORDER] = {};
+    void *fhat[CPRAND_MAX_ORDER] = {};
+    double *lambda = nullptr;
+    void *wpart = nullptr;
+    void *rpart = nullptr;
+    double *vpart = nullptr;
+    double *vrpart = nullptr;
+    double *colsq = nullptr;
+    double *fitpart = nullptr;
+    double *normpart = nullptr;
+    double *normX = nullptr;
+    double *hist_dev = nullptr;
+    double *hist_host = nullptr;
+    void *wtmp = nullptr;
+    void *ysum = nullptr;
+    uint64_t *t_dev = nullptr;
+    int32_t *info = nullptr;
+    int64_t *seg_off = nullptr;
+    std::vector<void *> allocs;
+    hipStream_t cap = nullptr;
+    hipEvent_t ev[4] = {};
+    // setup timing: [0,1] norm, [2+2m, 3+2m] mix pass m, [2+2N+2m, 3+2N+2m] layout copy m
+    hipEvent_t tev[2 + 4 * CPRAND_MAX_ORDER] = {};
+    ~cprand_plan() {
+        for (void *p : allocs) (void)hipFree(p);
+        if (hist_host) (void)hipHostFree(hist_host);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto &e : tev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+hipError_t dalloc(cprand_plan *p, void **ptr, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e == hipSuccess) p->allocs.push_back(*ptr);
+    return e;
+}
+
+int vec_elems(int kind) { return (int)(16 / elem_size(kind)); }
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// host stopping rule, identical in meaning to the reference: stop after
+// iteration t (0-based) when t+1 >= max_iters, |F_t - F_{t-1}| <= tol,
+// F_t >= fit_target, or the best F has not improved for `patience` steps.
+struct Stop {
+    const cprand_opts &o;
+    bool have_prev = false;
+    double prev = 0, best = -INFINITY;
+    int since = 0;
+    explicit Stop(const cprand_opts &oo) : o(oo) {}
+    bool operator()(int t, double F) {
+        bool stop = t + 1 >= o.max_iters;
+        if (o.tol > 0 && have_prev && fabs(F - prev) <= o.tol) stop = true;
+        if (o.fit_target <= 1.0 && F >= o.fit_target) stop = true;
+        if (F > best) {
+            best = F;
+            since = 0;
+        } else {
+            ++since;
+            if (o.patience > 0 && since >= o.patience) stop = true;
+        }
+        prev = F;
+        have_prev = true;
+        return stop;
+    }
+};
+
+const void *view_ptr(const cprand_plan *p, const View &v, const void *xdata) {
+    if (v.data) return v.data;
+    return v.from_xhat ? p->xhat : xdata;
+}
+
+// One outer iteration on `st`.
+hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CPRAND_MAX_ORDER], hipStream_t st) {
+    hipError_t e = hipSuccess;
+    const int N = p->N, R = p->o.R;
+    for (int n = 0; n < N && e == hipSuccess; ++n) {
+        const View &v = p->gview[n];
+        const void *vd = view_ptr(p, v, xdata);
+        GatherPlan gp = plan_gather(p->gkind, R, p->o.S, p->dims[n],
+                                    v.data ? true : contig_x[n]);
+        GatherArgs ga{};
+        ga.mi.order = N;
+        ga.mi.n = n;
+        for (int m = 0; m < N; ++m) {
+            ga.mi.dims[m] = p->dims[m];
+            ga.mi.strides[m] = v.strides[m];
+            ga.A.p[m] = (m == n) ? nullptr : (p->mix ? p->fhat[m] : p->fac[m]);
+        }
+        ga.X = vd;
+        CdfPtrs cdf{};
+        if (p->o.proposal == CPRAND_PROPOSAL_TABLE) {
+            for (int m = 0; m < N; ++m) cdf.p[m] = p->o.proposal_cdf[m];
+            ga.cdf = &cdf;
+        }
+        ga.seed = p->o.seed;
+        ga.t_dev = p->t_dev;
+        ga.wpart = p->wpart;
+        ga.vpart = p->vpart;
+        e = launch_gather(gp, ga, st);
+        GatherPlan gr{};
+        if (e == hipSuccess && p->refine) {
+            const View &rv = p->rview[n];
+            gr = plan_gather(K_F32, R, p->o.S, p->dims[n], rv.data ? true : contig_x[n]);
+            GatherArgs g2 = ga;
+            for (int m = 0; m < N; ++m) g2.mi.strides[m] = rv.strides[m];
+            g2.X = view_ptr(p, rv, xdata);
+            g2.wpart = p->rpart;
+            g2.vpart = p->vrpart;
+            e = launch_gather(gr, g2, st);
+        }
+        const int64_t In = p->dims[n];
+        SolveArgs sa{};
+        sa.In = (int32_t)In;
+        sa.R = R;
+        sa.vpart = p->vpart;
+        sa.vparts = gp.chunks;
+        if (p->mix) {
+            const void *y = p->wpart;
+            int32_t np = gp.chunks;
+            if (e == hipSuccess && np > 8) {
+                e = launch_sum_parts(p->wpart, np, (int64_t)2 * R * In, p->dbl, p->ysum, st);
+                y = p->ysum;
+                np = 1;
+            }
+            if (e == hipSuccess) {
+                FftPlan *fp = fft_plan_get(In, p->dbl, &e);
+                if (fp) e = launch_unmix(fp, p->dbl, (int32_t)In, R, np, y, p->signs + p->seg_off[n], p->wtmp, false, st);
+            }
+            sa.W = p->wtmp;
+            sa.wparts = 1;
+            sa.wps = 0;
+        } else {
+            sa.W = p->wpart;
+            sa.wparts = gp.chunks;
+            sa.wps = (int64_t)R * In;
+        }
+        sa.wsi = 1;
+        sa.wsr = In;
+        sa.wdouble = p->dbl;
+        if (p->refine) {
+            sa.Wref = (const float *)p->rpart;
+            sa.wrefparts = gr.chunks;
+            sa.rps = (int64_t)R * In;
+            sa.rsi = 1;
+            sa.rsr = In;
+        }
+        sa.A = p->fac[n];
+        sa.adouble = p->dbl;
+        sa.colsq_part = p->colsq;
+        sa.info = p->info;
+        sa.info_sticky = 1;
+        int32_t nb = 0;
+        if (e == hipSuccess) e = launch_solve(sa, &nb, st);
+        if (e == hipSuccess) e = launch_normalize((int32_t)In, R, p->fac[n], p->dbl, p->colsq, nb, p->lambda, st);
+        if (e == hipSuccess && p->mix) {
+            FftPlan *fp = fft_plan_get(In, p->dbl, &e);
+            if (fp) e = launch_factor_mix(fp, p->dbl, (int32_t)In, R, p->fac[n], p->signs + p->seg_off[n], p->fhat[n],
+                                          false, st);
+        }
+    }
+    if (e != hipSuccess) return e;
+    FitArgs fa{};
+    fa.mi.order = N;
+    for (int m = 0; m < N; ++m) {
+        fa.mi.dims[m] = p->dims[m];
+        fa.mi.strides[m] = p->mix ? 0 : p->xstrides[m];
+        fa.A.p[m] = p->mix ? p->fhat[m] : p->fac[m];
+    }
+    if (p->mix) {
+        int64_t s = 1;
+        for (int m = 0; m < N; ++m) {
+            fa.mi.strides[m] = s;
+            s *= p->dims[m];
+        }
+        fa.X = p->xhat;
+        fa.kind = p->dbl ? K_C128 : K_C64;
+        fa.cplx = true;
+    } else {
+        fa.X = xdata;
+        fa.kind = p->xkind;
+        fa.cplx = false;
+    }
+    fa.fdouble = p->dbl;
+    fa.lambda = p->lambda;
+    fa.R = R;
+    fa.P_hat = p->o.P_hat;
+    fa.seed = p->o.seed;
+    fa.part = p->fitpart;
+    int32_t nb = 0;
+    e = launch_fit_partial(fa, &nb, st);
+    if (e == hipSuccess)
+        e = launch_fit_final(p->fitpart, nb, p->o.P_hat, (double)p->P, p->normX, nullptr, p->hist_dev, p->t_dev, st);
+    if (e == hipSuccess) e = launch_inc_u64(p->t_dev, st);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_plan **plan_out) {
+    g_last_error.clear();
+    if (!plan_out) return set_error(CPRAND_EINVAL, "plan is NULL");
+    *plan_out = nullptr;
+    if (!X || !opts) return set_error(CPRAND_EINVAL, "X and opts must be non-NULL");
+    if (X->order < 2 || X->order > CPRAND_MAX_ORDER) return set_error(CPRAND_EINVAL, "order outside [2, 8]");
+    const int xk = kind_of(X->dtype);
+    if (xk != K_F32 && xk != K_F64) return set_error(CPRAND_EINVAL, "X must be F32 or F64");
+    for (int m = 0; m < X->order; ++m) {
+        if (X->dims[m] < 1 || X->dims[m] > (int64_t)INT32_MAX) return set_error(CPRAND_EINVAL, "dims[%d] invalid", m);
+        if (X->strides[m] < 1) return set_error(CPRAND_EINVAL, "strides[%d] < 1", m);
+    }
+    const cprand_opts &o = *opts;
+    if (o.R < 1 || o.R > CPRAND_MAX_RANK) return set_error(CPRAND_EINVAL, "R = %d outside [1, %d]", o.R, CPRAND_MAX_RANK);
+    if (o.S < 1) return set_error(CPRAND_EINVAL, "S = %d < 1", o.S);
+    if (o.P_hat < 1) return set_error(CPRAND_EINVAL, "P_hat = %d < 1", o.P_hat);
+    if (o.max_iters < 1) return set_error(CPRAND_EINVAL, "max_iters = %d < 1", o.max_iters);
+    if (o.mix != CPRAND_MIX_NONE && o.mix != CPRAND_MIX_FFT) return set_error(CPRAND_EINVAL, "mix = %d", o.mix);
+    if (o.precision < 0 || o.precision > 2) return set_error(CPRAND_EINVAL, "precision = %d", o.precision);
+    if (o.precision != CPRAND_PREC_NATIVE && xk != K_F32)
+        return set_error(CPRAND_EINVAL, "the BF16 form reads an F32 tensor");
+    if (o.precision != CPRAND_PREC_NATIVE && o.mix) return set_error(CPRAND_EUNSUPPORTED, "BF16 with mixing");
+    if (o.proposal == CPRAND_PROPOSAL_TABLE) {
+        if (!o.proposal_cdf) return set_error(CPRAND_EINVAL, "PROPOSAL_TABLE needs proposal_cdf");
+        for (int m = 0; m < X->order; ++m)
+            if (!o.proposal_cdf[m]) return set_error(CPRAND_EINVAL, "proposal_cdf[%d] is NULL", m);
+        if (o.mix) return set_error(CPRAND_EUNSUPPORTED, "importance sampling with mixing");
+    } else if (o.proposal != CPRAND_PROPOSAL_UNIFORM) {
+        return set_error(CPRAND_EUNSUPPORTED, "proposal %d not available in this build", o.proposal);
+    }
+    if (o.mix && !is_colmajor(X)) return set_error(CPRAND_EUNSUPPORTED, "mixing needs a column-major X");
+    cprand_plan *p = new cprand_plan();
+    p->o = o;
+    p->N = X->order;
+    p->xkind = xk;
+    p->dbl = xk == K_F64;
+    p->mix = o.mix == CPRAND_MIX_FFT;
+    p->bf16 = o.precision != CPRAND_PREC_NATIVE;
+    p->refine = o.precision == CPRAND_PREC_BF16_REFINE;
+    for (int m = 0; m < p->N; ++m) {
+        p->dims[m] = X->dims[m];
+        p->xstrides[m] = X->strides[m];
+        p->P *= X->dims[m];
+    }
+    const int N = p->N, R = o.R;
+    if (p->mix) {
+        for (int m = 0; m < N; ++m) {
+            hipError_t fe;
+            if (!fft_plan_get(p->dims[m], p->dbl, &fe)) {
+                delete p;
+                return set_error(CPRAND_EUNSUPPORTED, "mode %d length %lld does not factor into 2,3,5,7", m,
+                                 (long long)X->dims[m]);
+            }
+        }
+    }
+    p->gkind = p->mix ? (p->dbl ? K_C128 : K_C64) : (p->bf16 ? K_BF16 : xk);
+    hipError_t e = hipSuccess;
+    const size_t tsz = p->dbl ? 8 : 4;
+    auto alloc_copy = [&](View &v, int kind, int n) -> hipError_t {
+        v.own = true;
+        v.kind = kind;
+        v.ld = round_up(p->dims[n], vec_elems(kind));
+        cprand_mode_major_strides(N, p->dims, n, v.ld, v.strides);
+        return dalloc(p, &v.data, (size_t)(p->P / p->dims[n]) * v.ld * elem_size(kind));
+    };
+    if (p->mix) {
+        e = dalloc(p, &p->xhat, (size_t)p->P * elem_size(p->gkind));
+        int64_t s = 1;
+        for (int n = 0; n < N && e == hipSuccess; ++n) {
+            View &v = p->gview[n];
+            const bool use_xhat = o.layout == 1 || (n == 0 && p->dims[0] % vec_elems(p->gkind) == 0);
+            if (use_xhat) {
+                v.from_xhat = true;
+                v.kind = p->gkind;
+                int64_t st = 1;
+                for (int m = 0; m < N; ++m) {
+                    v.strides[m] = st;
+                    st *= p->dims[m];
+                }
+            } else {
+                e = alloc_copy(v, p->gkind, n);
+            }
+        }
+        (void)s;
+    } else {
+        for (int n = 0; n < N && e == hipSuccess; ++n) {
+            if (p->bf16) {
+                e = alloc_copy(p->gview[n], K_BF16, n);
+                if (e != hipSuccess) break;
+            }
+            View &v = p->bf16 ? p->rview[n] : p->gview[n];
+            if (p->bf16 && !p->refine) continue;
+            const int ve = vec_elems(xk);
+            bool ok = o.layout == 1 || X->strides[n] == 1;
+            for (int m = 0; m < N && ok && o.layout != 1; ++m)
+                if (m != n && X->strides[m] % ve) ok = false;
+            if (ok) {
+                v.kind = xk;
+                for (int m = 0; m < N; ++m) v.strides[m] = X->strides[m];
+            } else {
+                if (!is_colmajor(X)) {
+                    delete p;
+                    return set_error(CPRAND_EUNSUPPORTED, "layout copies read a column-major X");
+                }
+                e = alloc_copy(v, xk, n);
+            }
+        }
+    }
+    if (e == hipSuccess) {
+        int64_t tot = 0;
+        for (int m = 0; m < N; ++m) tot += p->dims[m];
+        e = dalloc(p, (void **)&p->signs, (size_t)tot);
+        p->seg_off = new int64_t[N];
+        int64_t off = 0;
+        for (int m = 0; m < N; ++m) {
+            p->seg_off[m] = off;
+            off += p->dims[m];
+        }
+    }
+    size_t wpart = 0, vpart = 0, rpart = 0;
+    int64_t maxdim = 1;
+    for (int n = 0; n < N; ++n) {
+        GatherPlan gp = plan_gather(p->gkind, R, o.S, p->dims[n], true);
+        const size_t gts = (p->gkind == K_F64 || p->gkind == K_C128) ? 8 : 4;
+        wpart = std::max(wpart, gp.wpart_elems() * gts);
+        vpart = std::max(vpart, gp.vpart_elems() * 8);
+        if (p->refine) {
+            GatherPlan gr = plan_gather(K_F32, R, o.S, p->dims[n], true);
+            rpart = std::max(rpart, gr.wpart_elems() * 4);
+        }
+        maxdim = std::max(maxdim, p->dims[n]);
+    }
+    for (int m = 0; m < N && e == hipSuccess; ++m) {
+        e = dalloc(p, &p->fac[m], (size_t)p->dims[m] * R * tsz);
+        if (e == hipSuccess && p->mix) e = dalloc(p, &p->fhat[m], (size_t)p->dims[m] * R * tsz * 2);
+    }
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->lambda, (size_t)R * 8);
+    if (e == hipSuccess) e = dalloc(p, &p->wpart, wpart);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->vpart, vpart);
+    if (e == hipSuccess && p->refine) e = dalloc(p, &p->rpart, rpart);
+    if (e == hipSuccess && p->refine) e = dalloc(p, (void **)&p->vrpart, vpart * 2 + 256);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->colsq, (size_t)ceil_div(maxdim, 32) * R * 8);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->fitpart, (size_t)ceil_div(o.P_hat, 256) * 8);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->normpart, 4096 * 8);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->normX, 8);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->hist_dev, (size_t)o.max_iters * 8);
+    if (e == hipSuccess) e = dalloc(p, &p->wtmp, (size_t)maxdim * R * tsz);
+    if (e == hipSuccess && p->mix) e = dalloc(p, &p->ysum, (size_t)maxdim * 2 * R * tsz);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->t_dev, 8);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->info, 8);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&p->hist_host, (size_t)o.max_iters * 8, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&p->ev[i]);
+    for (int i = 0; i < 2 + 4 * CPRAND_MAX_ORDER && e == hipSuccess; ++i) e = hipEventCreate(&p->tev[i]);
+    if (e != hipSuccess) {
+        delete p;
+        if (e == hipErrorOutOfMemory) return set_error(CPRAND_ENOMEM, "device allocation failed");
+        return hip_fail(e, "plan allocation");
+    }
+    *plan_out = p;
+    return CPRAND_OK;
+}
+
+void cprand_plan_destroy(cprand_plan *plan) {
+    if (!plan) return;
+    delete[] plan->seg_off;
+    delete plan;
+}
+
+int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout, double *lambda_out,
+                    cprand_report *rep, void *stream) {
+    g_last_error.clear();
+    if (!p) return set_error(CPRAND_EINVAL, "plan is NULL");
+    int rc = check_tensor(X, "X");
+    if (rc) return rc;
+    if (X->order != p->N || kind_of(X->dtype) != p->xkind) return set_error(CPRAND_EINVAL, "X differs from the plan");
+    for (int m = 0; m < p->N; ++m)
+        if (X->dims[m] != p->dims[m] || X->strides[m] != p->xstrides[m])
+            return set_error(CPRAND_EINVAL, "X shape or strides differ from the plan");
+    if (!A_inout || !lambda_out) return set_error(CPRAND_EINVAL, "A_inout and lambda_out must be non-NULL");
+    for (int m = 0; m < p->N; ++m)
+        if (!A_inout[m]) return set_error(CPRAND_EINVAL, "A_inout[%d] is NULL", m);
+    hipStream_t st = (hipStream_t)stream;
+    const int N = p->N, R = p->o.R;
+    const size_t tsz = p->dbl ? 8 : 4;
+    hipError_t e = hipSuccess;
+    bool contig_x[CPRAND_MAX_ORDER];
+    for (int n = 0; n < N; ++n) {
+        const View &v = p->mix ? p->gview[n] : (p->bf16 ? p->rview[n] : p->gview[n]);
+        contig_x[n] = fibers_vectorizable(p->mix ? p->xhat : X->data, p->mix ? p->gkind : p->xkind, v.strides, N, n);
+    }
+
+    e = hipEventRecord(p->ev[0], st);
+    for (int m = 1; m < N && e == hipSuccess; ++m)
+        e = hipMemcpyAsync(p->fac[m], A_inout[m], (size_t)p->dims[m] * R * tsz, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = launch_fill_u64(p->t_dev, 0, st);
+    if (e == hipSuccess) e = launch_fill_u64((uint64_t *)p->info, 0, st);
+    ModeInfo xi = mode_info(X, 0);
+    bool timed_mix[CPRAND_MAX_ORDER] = {}, timed_lay[CPRAND_MAX_ORDER] = {};
+    hipEvent_t *tev = p->tev;
+    if (e == hipSuccess) {
+        int32_t np = 0;
+        e = hipEventRecord(tev[0], st);
+        if (e == hipSuccess) e = launch_normsq_partial(xi, X->data, p->xkind, p->normpart, &np, st);
+        if (e == hipSuccess) e = launch_sqrt_sum(p->normpart, np, p->normX, st);
+        if (e == hipSuccess) e = hipEventRecord(tev[1], st);
+    }
+    if (e == hipSuccess && p->mix) {
+        e = launch_signs(xi, p->o.seed, p->signs, st);
+        for (int m = 0; m < N && e == hipSuccess; ++m) {
+            FftPlan *fp = fft_plan_get(p->dims[m], p->dbl, &e);
+            if (fp) e = hipEventRecord(tev[2 + 2 * m], st);
+            if (fp && e == hipSuccess)
+                e = launch_mix_pass(fp, p->dbl, xi, X->data, p->xkind, p->xhat, m, m == 0, p->signs, nullptr, nullptr, st);
+            if (fp && e == hipSuccess) e = hipEventRecord(tev[3 + 2 * m], st);
+            timed_mix[m] = e == hipSuccess;
+        }
+        cprand_tensor xh{};
+        xh.order = N;
+        xh.dtype = p->dbl ? CPRAND_C128 : CPRAND_C64;
+        int64_t s = 1;
+        for (int m = 0; m < N; ++m) {
+            xh.dims[m] = p->dims[m];
+            xh.strides[m] = s;
+            s *= p->dims[m];
+        }
+        xh.data = p->xhat;
+        ModeInfo hi = mode_info(&xh, 0);
+        for (int n = 0; n < N && e == hipSuccess; ++n)
+            if (p->gview[n].own) {
+                e = hipEventRecord(tev[2 + 2 * N + 2 * n], st);
+                if (e == hipSuccess)
+                    e = launch_layout_copy(hi, p->xhat, p->gkind, n, p->gview[n].ld, p->gview[n].data, p->gkind, st);
+                if (e == hipSuccess) e = hipEventRecord(tev[3 + 2 * N + 2 * n], st);
+                timed_lay[n] = e == hipSuccess;
+            }
+        for (int m = 1; m < N && e == hipSuccess; ++m) {
+            FftPlan *fp = fft_plan_get(p->dims[m], p->dbl, &e);
+            if (fp) e = launch_factor_mix(fp, p->dbl, (int32_t)p->dims[m], R, p->fac[m], p->signs + p->seg_off[m],
+                                          p->fhat[m], false, st);
+        }
+    } else if (e == hipSuccess) {
+        for (int n = 0; n < N && e == hipSuccess; ++n) {
+            const bool any = p->gview[n].own || (p->refine && p->rview[n].own);
+            if (any) e = hipEventRecord(tev[2 + 2 * N + 2 * n], st);
+            if (e == hipSuccess && p->gview[n].own)
+                e = launch_layout_copy(xi, X->data, p->xkind, n, p->gview[n].ld, p->gview[n].data, p->gview[n].kind, st);
+            if (e == hipSuccess && p->refine && p->rview[n].own)
+                e = launch_layout_copy(xi, X->data, p->xkind, n, p->rview[n].ld, p->rview[n].data, p->rview[n].kind, st);
+            if (any && e == hipSuccess) e = hipEventRecord(tev[3 + 2 * N + 2 * n], st);
+            timed_lay[n] = any && e == hipSuccess;
+        }
+    }
+    if (e == hipSuccess) e = hipEventRecord(p->ev[1], st);
+    if (e != hipSuccess) return hip_fail(e, "setup");
+
+    // the ALS loop
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (p->o.use_graph) {
+        e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            hipError_t e2 = enqueue_iteration(p, X->data, contig_x, p->cap);
+            e = hipStreamEndCapture(p->cap, &graph);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(e, "graph capture");
+        }
+    }
+    Stop stop(p->o);
+    int it = 0;
+    double F = 0.0;
+    for (; it < p->o.max_iters; ++it) {
+        e = exec ? hipGraphLaunch(exec, st) : enqueue_iteration(p, X->data, contig_x, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(p->hist_host + it, p->hist_dev + it, 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipEventRecord(p->ev[2], st);
+        if (e == hipSuccess) e = hipEventSynchronize(p->ev[2]);
+        if (e != hipSuccess) break;
+        F = p->hist_host[it];
+        if (!isfinite(F)) {
+            e = hipErrorUnknown;
+            break;
+        }
+        if (stop(it, F)) {
+            ++it;
+            break;
+        }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess && isfinite(F)) return hip_fail(e, "ALS loop");
+    if (!isfinite(F)) return set_error(CPRAND_ENAN, "non-finite fit estimate at iteration %d", it);
+    hipEventRecord(p->ev[3], st);
+    for (int m = 0; m < N && e == hipSuccess; ++m)
+        e = hipMemcpyAsync(A_inout[m], p->fac[m], (size_t)p->dims[m] * R * tsz, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(lambda_out, p->lambda, (size_t)R * 8, hipMemcpyDeviceToDevice, st);
+    int32_t info = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&info, p->info, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "results");
+    int flags = info ? CPRAND_W_PINV : 0;
+    if (it >= p->o.max_iters) flags |= CPRAND_W_MAXIT;
+    if (rep) {
+        rep->iters = it;
+        rep->flags = flags;
+        rep->fit_est = F;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, p->ev[0], p->ev[1]);
+        rep->setup_ms = ms;
+        (void)hipEventElapsedTime(&ms, p->ev[1], p->ev[3]);
+        rep->loop_ms = ms;
+        (void)hipEventElapsedTime(&ms, tev[0], tev[1]);
+        rep->norm_ms = ms;
+        for (int m = 0; m < CPRAND_MAX_ORDER; ++m) {
+            rep->mix_ms[m] = 0.0;
+            rep->layout_ms[m] = 0.0;
+            if (m < N && timed_mix[m] && hipEventElapsedTime(&ms, tev[2 + 2 * m], tev[3 + 2 * m]) == hipSuccess)
+                rep->mix_ms[m] = ms;
+            if (m < N && timed_lay[m] &&
+                hipEventElapsedTime(&ms, tev[2 + 2 * N + 2 * m], tev[3 + 2 * N + 2 * m]) == hipSuccess)
+                rep->layout_ms[m] = ms;
+        }
+        if (rep->fit_history) memcpy(rep->fit_history, p->hist_host, (size_t)it * 8);
+        if (rep->proposal_history)
+            for (int i = 0; i < it; ++i) rep->proposal_history[i] = p->o.proposal;
+    }
+    return flags;
+}
+
+int cprand_als(const cprand_tensor *X, const cprand_opts *opts, void *const *A_inout, double *lambda_out,
+               cprand_report *report, void *stream) {
+    cprand_plan *p = nullptr;
+    int rc = cprand_plan_create(X, opts, &p);
+    if (rc < 0) return rc;
+    rc = cprand_plan_run(p, X, A_inout, lambda_out, report, stream);
+    cprand_plan_destroy(p);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+// Sampled fit estimate (Section 3.4) and the tensor norm.
+//
+// One thread per sampled entry: it regenerates the entry's multi-index from
+// Philox (so the set is the same at every call), loads the tensor element,
+// evaluates the model entry sum_r lambda_r prod_m A^(m)(i_m, r) from the
+// L2-resident factor rows and squares the error; FP64 throughout, fixed-order
+// block sums, and a one-block final kernel.
+#include <math.h>
+
+#include "kernels.hpp"
+
+namespace cprand {
+
+constexpr int kFitThreads = 256;
+
+__device__ inline void load_elem(const void *X, int kind, int64_t o, double &re, double &im) {
+    im = 0.0;
+    switch (kind) {
+        case K_F64: re = ((const double *)X)[o]; break;
+        case K_F32: re = (double)((const float *)X)[o]; break;
+        case K_BF16: re = (double)bf16_to_f32(((const uint16_t *)X)[o]); break;
+        case K_C64:
+            re = (double)((const float *)X)[2 * o];
+            im = (double)((const float *)X)[2 * o + 1];
+            break;
+        default:
+            re = ((const double *)X)[2 * o];
+            im = ((const double *)X)[2 * o + 1];
+            break;
+    }
+}
+
+__global__ __launch_bounds__(kFitThreads) void fit_partial_kernel(FitArgs a) {
+    __shared__ double sh[kFitThreads / kWave];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double e2 = 0.0;
+    if (p < a.P_hat) {
+        const int N = a.mi.order;
+        int64_t row[kMaxOrder];
+        u64x4 blk;
+        int64_t off = 0;
+        for (int k = 0; k < N; ++k) {
+            if ((k & 3) == 0) blk = philox4x64_10((uint64_t)p, 0, 0, (uint64_t)(k >> 2), a.seed, kTagFit);
+            row[k] = (int64_t)mulhi64(blk.v[k & 3], (uint64_t)a.mi.dims[k]);
+            off += row[k] * a.mi.strides[k];
+        }
+        double xr, xi;
+        load_elem(a.X, a.kind, off, xr, xi);
+        double mr = 0.0, mi = 0.0;
+        for (int r = 0; r < a.R; ++r) {
+            double zr = a.lambda[r], zi = 0.0;
+            for (int m = 0; m < N; ++m) {
+                const int64_t o = row[m] * a.R + r;
+                if (!a.cplx) {
+                    zr *= a.fdouble ? ((const double *)a.A.p[m])[o] : (double)((const float *)a.A.p[m])[o];
+                } else {
+                    double ar, ai;
+                    if (a.fdouble) {
+                        ar = ((const double *)a.A.p[m])[2 * o];
+                        ai = ((const double *)a.A.p[m])[2 * o + 1];
+                    } else {
+                        ar = (double)((const float *)a.A.p[m])[2 * o];
+                        ai = (double)((const float *)a.A.p[m])[2 * o + 1];
+                    }
+                    const double nr = zr * ar - zi * ai, ni = zr * ai + zi * ar;
+                    zr = nr;
+                    zi = ni;
+                }
+            }
+            mr += zr;
+            mi += zi;
+        }
+        const double dr = xr - mr, di = xi - mi;
+        e2 = dr * dr + di * di;
+    }
+    const double s = block_sum<kFitThreads>(e2, sh);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = s;
+}
+
+hipError_t launch_fit_partial(const FitArgs &a, int32_t *nblocks, hipStream_t st) {
+    const int nb = (int)ceil_div(a.P_hat, kFitThreads);
+    *nblocks = nb;
+    hipLaunchKernelGGL(fit_partial_kernel, dim3(nb), dim3(kFitThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+__global__ void fit_final_kernel(const double *part, int32_t nparts, int32_t P_hat, double P,
+                                 const double *normX, double *fit_out, double *hist,
+                                 const uint64_t *t_dev) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += part[i];
+    const double mu = s / (double)P_hat;
+    const double f = 1.0 - sqrt(P * mu) / *normX;
+    if (fit_out) *fit_out = f;
+    if (hist) hist[t_dev ? *t_dev : 0] = f;
+}
+
+hipError_t launch_fit_final(const double *part, int32_t nparts, int32_t P_hat, double P,
+                            const double *normX, double *fit_out, double *hist,
+                            const uint64_t *t_dev, hipStream_t st) {
+    hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(64), 0, st, part, nparts, P_hat, P, normX,
+                       fit_out, hist, t_dev);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// sum of squares; every block covers a fixed contiguous range of the logical
+// (column-major) element order, so the result does not depend on timing.
+constexpr int kNormBlocks = 1024;
+
+__global__ __launch_bounds__(256) void normsq_kernel(ModeInfo mi, const void *X, int kind,
+                                                     int64_t P, int contiguous, double *part) {
+    __shared__ double sh[256 / kWave];
+    const int64_t per = ceil_div(P, (int64_t)gridDim.x);
+    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(P, b0 + per);
+    double acc = 0.0;
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
+        int64_t off = e;
+        if (!contiguous) {
+            int64_t rem = e;
+            off = 0;
+            for (int m = 0; m < mi.order; ++m) {
+                const int64_t im = rem % mi.dims[m];
+                rem /= mi.dims[m];
+                off += im * mi.strides[m];
+            }
+        }
+        double re, im;
+        load_elem(X, kind, off, re, im);
+        acc += re * re + im * im;
+    }
+    const double s = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+hipError_t launch_normsq_partial(const ModeInfo &mi, const void *X, int kind, double *part,
+                                 int32_t *nparts, hipStream_t st) {
+    int64_t P = 1, expect = 1;
+    bool contiguous = true;
+    for (int m = 0; m < mi.order; ++m) {
+        if (mi.strides[m] != expect) contiguous = false;
+        expect *= mi.dims[m];
+        P *= mi.dims[m];
+    }
+    *nparts = kNormBlocks;
+    hipLaunchKernelGGL(normsq_kernel, dim3(kNormBlocks), dim3(256), 0, st, mi, X, kind, P,
+                       contiguous ? 1 : 0, part);
+    return hipGetLastError();
+}
+
+__global__ void sqrt_sum_kernel(const double *part, int32_t n, double *out) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = sqrt(s);
+}
+
+hipError_t launch_sqrt_sum(const double *part, int32_t nparts, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(sqrt_sum_kernel, dim3(1), dim3(64), 0, st, part, nparts, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void fill_u64_kernel(uint64_t *p, uint64_t v) {
+    if (threadIdx.x == 0) *p = v;
+}
+__global__ void inc_u64_kernel(uint64_t *p) {
+    if (threadIdx.x == 0) *p += 1;
+}
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, hipStream_t st) {
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, p, v);
+    return hipGetLastError();
+}
+hipError_t launch_inc_u64(uint64_t *p, hipStream_t st) {
+    hipLaunchKernelGGL(inc_u64_kernel, dim3(1), dim3(64), 0, st, p);
+    return hipGetLastError();
+}
+
+}  // namespace cprand

@@ -1,0 +1,139 @@
+// Host-side launchers of the HIP kernels (one .hip file per family).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace cprand {
+
+// ---- sampling ---------------------------------------------------------------
+hipError_t launch_sample(const ModeInfo &mi, int32_t S, uint64_t seed, uint64_t t,
+                         const uint64_t *t_dev, const CdfPtrs *cdf, int32_t *idx, double *w,
+                         hipStream_t st);
+
+// ---- sampled MTTKRP -----------------------------------------------------------
+// Element kinds of the gathered tensor.
+enum Kind { K_F64 = 0, K_F32 = 1, K_BF16 = 2, K_C64 = 3, K_C128 = 4 };
+
+struct GatherPlan {
+    int kind;
+    int32_t R, S, In;
+    int32_t ncols;      // R (real) or 2R (complex)
+    int32_t ct;         // column tiles of 16
+    int32_t kc;         // samples per chunk
+    int32_t chunks;     // gridDim.y
+    int32_t rows_wg;    // rows per workgroup
+    int32_t waves;      // waves per workgroup
+    int32_t row_blocks; // gridDim.x
+    bool contig;        // vector loads along the fiber
+    size_t lds_bytes;
+    size_t wpart_elems() const { return (size_t)chunks * (size_t)ncols * (size_t)In; }
+    size_t vpart_elems() const { return (size_t)chunks * (size_t)R * (size_t)R; }
+};
+
+// Choose tiling for one mode step.  elem_align: true when the data pointer
+// and every stride other than mode n allow 16-byte vector loads along fibers.
+GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_ok);
+
+struct GatherArgs {
+    ModeInfo mi;
+    const void *X;
+    FactorPtrs A;        // row-major I_m x R, real type (complex interleaved for mixed)
+    const int32_t *idx;  // S x order, or NULL: draw in-kernel
+    const double *w;     // S weights or NULL (only with idx)
+    const CdfPtrs *cdf;  // NULL or proposal tables for in-kernel draws (host struct, copied)
+    uint64_t seed, t;
+    const uint64_t *t_dev;
+    void *wpart;         // [chunks][ncols][In] real type (float for BF16)
+    double *vpart;       // [chunks][R][R]
+};
+
+hipError_t launch_gather(const GatherPlan &gp, const GatherArgs &a, hipStream_t st);
+
+// out[e] = sum_p parts[p*count + e] (fixed order), float or double.
+hipError_t launch_sum_parts(const void *parts, int32_t np, int64_t count, bool dbl, void *out, hipStream_t st);
+
+// Sum partials into row-major W (In x R, real type) and V (R x R).  For real
+// kinds only (complex ones go through launch_unmix).
+hipError_t launch_reduce_wv(const GatherPlan &gp, const void *wpart, const double *vpart,
+                            void *W, double *V, hipStream_t st);
+
+// ---- FFT-based mixing -------------------------------------------------------------
+struct FftPlan;  // per-length twiddles and radix schedule on the device
+FftPlan *fft_plan_get(int64_t L, bool dbl, hipError_t *err);  // cached per (L, precision, device)
+
+// Unmix the complex partial sums Y (chunks x 2R x In) of one mode step:
+// W[i][r] = sign[i] Re( (F^* y_r)[i] ), y_r = sum over chunks.  W row-major
+// (In x R) when w_rowmajor, else column-major [R][In].
+hipError_t launch_unmix(const FftPlan *fp, bool dbl, int32_t In, int32_t R, int32_t chunks,
+                        const void *ypart, const int8_t *sign, void *W, bool w_rowmajor,
+                        hipStream_t st);
+// A-hat = F D A (inverse = false) or A = Re(D F^* A-hat) (inverse = true).
+hipError_t launch_factor_mix(const FftPlan *fp, bool dbl, int32_t I, int32_t R, const void *in,
+                             const int8_t *sign, void *out, bool inverse, hipStream_t st);
+// One pass of the tensor mix along mode m.  first: read the real input X
+// (any strides), apply all sign vectors and write column-major complex
+// Xhat; otherwise transform Xhat in place.  normsq_part: per-block partial
+// sums of x^2 (first pass only) or NULL.
+hipError_t launch_mix_pass(const FftPlan *fp, bool dbl, const ModeInfo &xi, const void *X,
+                           int xkind, void *Xhat, int32_t m, bool first, const int8_t *signs,
+                           double *normsq_part, int32_t *nparts, hipStream_t st);
+hipError_t launch_signs(const ModeInfo &mi, uint64_t seed, int8_t *signs, hipStream_t st);
+
+// ---- solve / normalise -------------------------------------------------------------
+struct SolveArgs {
+    int32_t In, R;
+    const double *vpart;   // parts x R x R
+    int32_t vparts;
+    const void *W;         // element (p, i, r) at W[p*wps + i*wsi + r*wsr]
+    int32_t wparts;
+    int64_t wps, wsi, wsr;
+    bool wdouble;          // W element type double (else float)
+    const float *Wref;     // refinement MTTKRP (p, i, r) at Wref[p*rps + i*rsi + r*rsr], or NULL
+    int32_t wrefparts;
+    int64_t rps, rsi, rsr;
+    void *A;               // row-major In x R, unnormalised on output of solve
+    bool adouble;
+    double *colsq_part;    // [blocks][R]
+    int32_t *info;         // device flag or NULL
+    int32_t info_sticky;   // 1: only ever set the flag; 0: also clear it on success
+};
+hipError_t launch_solve(const SolveArgs &a, int32_t *nblocks, hipStream_t st);
+hipError_t launch_normalize(int32_t In, int32_t R, void *A, bool adouble,
+                            const double *colsq_part, int32_t nblocks, double *lambda,
+                            hipStream_t st);
+
+// ---- fit ------------------------------------------------------------------------------
+struct FitArgs {
+    ModeInfo mi;          // dims/strides of X (n unused)
+    const void *X;
+    int kind;             // K_*
+    FactorPtrs A;         // real or complex (interleaved) factors
+    bool fdouble;         // factor real type
+    bool cplx;            // factors complex
+    const double *lambda;
+    int32_t R;
+    int32_t P_hat;
+    uint64_t seed;
+    double *part;         // per-block partial sums
+};
+hipError_t launch_fit_partial(const FitArgs &a, int32_t *nblocks, hipStream_t st);
+// fit_out = 1 - sqrt(P * sum(part)/P_hat) / *normX; also hist[t] (t from t_dev) if hist.
+hipError_t launch_fit_final(const double *part, int32_t nparts, int32_t P_hat, double P,
+                            const double *normX, double *fit_out, double *hist,
+                            const uint64_t *t_dev, hipStream_t st);
+hipError_t launch_normsq_partial(const ModeInfo &mi, const void *X, int kind, double *part,
+                                 int32_t *nparts, hipStream_t st);
+hipError_t launch_sqrt_sum(const double *part, int32_t nparts, double *out, hipStream_t st);
+
+// ---- layout --------------------------------------------------------------------------
+hipError_t launch_layout_copy(const ModeInfo &xi, const void *X, int xkind, int32_t n,
+                              int64_t ld, void *Y, int ykind, hipStream_t st);
+
+// ---- small helpers ---------------------------------------------------------------------
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, hipStream_t st);
+hipError_t launch_inc_u64(uint64_t *p, hipStream_t st);
+
+}  // namespace cprand

@@ -1,0 +1,439 @@
+// Sampled MTTKRP and Gram for one mode step (Alg. 2 and Alg. 3; complex
+// form for the mixed tensor of Alg. 4 / eq. rcLS).
+//
+// One workgroup owns a chunk of KC samples and a block of fiber rows.  It
+// (1) draws or loads the chunk's multi-indices and fiber base offsets,
+// (2) forms the sampled Khatri-Rao rows Z_S in LDS as Hadamard products of
+//     factor rows (the factors are small and stay in L2),
+// (3) for the first row block only, accumulates the chunk's Gram
+//     Z^T diag(w) Z in FP64,
+// (4) streams the chunk's fibers straight from HBM with 16-byte loads (one
+//     wave covers 16*VE consecutive rows of four fibers per step) into MFMA
+//     16x16x4 products against Z_S, FP32 or FP64 accumulation.
+// Each lane's 16-byte vector holds VE consecutive fiber rows; MFMA number c
+// takes component c, so the A operand needs no shuffle and the output rows
+// are a fixed permutation that the store undoes.  Partial products of every
+// chunk go to a workspace and are summed by the consumer in a fixed order
+// (deterministic results).
+#include "kernels.hpp"
+
+namespace cprand {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct AccT;
+template <>
+struct AccT<float> {
+    typedef v4f type;
+};
+template <>
+struct AccT<double> {
+    typedef v4d type;
+};
+
+__device__ inline v4f mfma16(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline v4d mfma16(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T, bool CPLX>
+struct Geo {
+    static constexpr int NV = 16 / (int)sizeof(T);          // reals per 16-byte vector
+    static constexpr int VE = CPLX ? NV / 2 : NV;          // fiber rows per lane per step
+    static constexpr int RPW = 16 * VE;                    // rows per wave per step
+};
+
+constexpr int kUnroll = 4;  // k-steps (of 4 samples) in flight per iteration
+
+// LDS row stride (in T) for the B operand: >= 16*CT and, for float, an odd
+// multiple of 16 words so that two B rows read by one half-wave hit
+// disjoint banks.
+__host__ __device__ constexpr int ldb_for(int ct, int tsize) {
+    return tsize == 4 ? (ct % 2 ? 16 * ct : 16 * ct + 16) : 16 * ct + 2;
+}
+
+struct KArgs {
+    ModeInfo mi;
+    const void *X;
+    FactorPtrs A;
+    const int32_t *idx;
+    const double *w;
+    CdfPtrs cdf;
+    int use_cdf;
+    uint64_t seed, t;
+    const uint64_t *t_dev;
+    void *wpart;
+    double *vpart;
+    int32_t R, S, In, ncols, kc, rows_wg;
+};
+
+template <typename T, bool CPLX, int CT, bool CONTIG, bool WEIGHTED>
+__global__ __launch_bounds__(256) void gather_contract(KArgs a) {
+    typedef Geo<T, CPLX> G;
+    typedef typename AccT<T>::type Acc;
+    constexpr int LDB = ldb_for(CT, (int)sizeof(T));
+    extern __shared__ __align__(16) unsigned char lds[];
+
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int KC = a.kc;
+    const int N = a.mi.order, n = a.mi.n;
+    const int R = a.R;
+    const int chunk = blockIdx.y;
+    const int s0 = chunk * KC;
+    const int ns = min(KC, a.S - s0);
+
+    // ---- LDS carve-up
+    int64_t *s_base = (int64_t *)lds;                      // KC
+    double *s_w = (double *)(s_base + KC);                 // KC
+    int32_t *s_idx = (int32_t *)(s_w + KC);                // KC x N
+    T *Bre = (T *)(lds + (((size_t)KC * (16 + 4 * N) + 15) & ~(size_t)15));
+    T *Bim = Bre + (size_t)KC * LDB;                       // complex only
+    T *Zr = CPLX ? Bre : (WEIGHTED ? Bre + (size_t)KC * LDB : Bre);  // raw z (real)
+
+    // ---- (1) indices, weights and fiber offsets
+    const uint64_t tt = a.t_dev ? *a.t_dev : a.t;
+    for (int sl = tid; sl < KC; sl += nthr) {
+        int64_t row[kMaxOrder];
+        double wv = 1.0;
+        int64_t base = 0;
+        if (sl < ns) {
+            const int64_t s = s0 + sl;
+            if (a.idx) {
+                for (int m = 0; m < N; ++m) row[m] = (m == n) ? 0 : a.idx[s * N + m];
+                if (a.w) wv = a.w[s];
+            } else {
+                wv = draw_sample(a.mi, a.seed, tt, s, a.use_cdf ? &a.cdf : nullptr, row);
+            }
+            for (int m = 0; m < N; ++m)
+                if (m != n) base += row[m] * a.mi.strides[m];
+        } else {
+            for (int m = 0; m < N; ++m) row[m] = 0;
+            wv = 0.0;
+        }
+        for (int m = 0; m < N; ++m) s_idx[sl * N + m] = (int32_t)row[m];
+        s_base[sl] = base;
+        s_w[sl] = wv;
+    }
+    // zero the B operand tiles (padding columns and samples stay zero)
+    {
+        const int words = (int)(((size_t)KC * LDB * sizeof(T) * ((CPLX || WEIGHTED) ? 2 : 1)) / 4);
+        uint32_t *p = (uint32_t *)Bre;
+        for (int e = tid; e < words; e += nthr) p[e] = 0u;
+    }
+    __syncthreads();
+
+    // ---- (2) sampled Khatri-Rao rows
+    for (int e = tid; e < ns * R; e += nthr) {
+        const int sl = e / R, r = e - sl * R;
+        if (!CPLX) {
+            T z = (T)1;
+            for (int m = 0; m < N; ++m) {
+                if (m == n) continue;
+                const T *Am = (const T *)a.A.p[m];
+                z *= Am[(int64_t)s_idx[sl * N + m] * R + r];
+            }
+            Zr[sl * LDB + r] = z;
+            if (WEIGHTED) Bre[sl * LDB + r] = (T)(s_w[sl] * (double)z);
+        } else {
+            T zr = (T)1, zi = (T)0;
+            for (int m = 0; m < N; ++m) {
+                if (m == n) continue;
+                const T *Am = (const T *)a.A.p[m];
+                const int64_t o = ((int64_t)s_idx[sl * N + m] * R + r) * 2;
+                const T ar = Am[o], ai = Am[o + 1];
+                const T nr = zr * ar - zi * ai;
+                const T ni = zr * ai + zi * ar;
+                zr = nr;
+                zi = ni;
+            }
+            // Y = X conj(Z): columns [0,R) real part, [R,2R) imaginary part
+            Bre[sl * LDB + r] = zr;
+            Bim[sl * LDB + r] = zi;
+            Bre[sl * LDB + R + r] = -zi;
+            Bim[sl * LDB + R + r] = zr;
+        }
+    }
+    __syncthreads();
+
+    // ---- (3) Gram of the chunk (first row block only), FP64, fixed order
+    if (blockIdx.x == 0) {
+        double *vp = a.vpart + (size_t)chunk * R * R;
+        for (int p = tid; p < R * R; p += nthr) {
+            const int r = p / R, q = p - r * R;
+            if (q < r) continue;
+            double acc = 0.0;
+            for (int sl = 0; sl < ns; ++sl) {
+                if (!CPLX) {
+                    double v = (double)Zr[sl * LDB + r] * (double)Zr[sl * LDB + q];
+                    if (WEIGHTED) v *= s_w[sl];
+                    acc += v;
+                } else {
+                    acc += (double)Bre[sl * LDB + r] * (double)Bre[sl * LDB + q] +
+                           (double)Bim[sl * LDB + r] * (double)Bim[sl * LDB + q];
+                }
+            }
+            vp[r * R + q] = acc;
+            vp[q * R + r] = acc;
+        }
+    }
+
+    // ---- (4) fibers x Z_S on MFMA
+    const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+    const int rowbase = blockIdx.x * a.rows_wg + wv * G::RPW;
+    if (rowbase >= a.In) return;
+    const int In = a.In;
+    const T *xp = (const T *)a.X;
+    const int64_t sn = a.mi.strides[n];
+    const int row0 = rowbase + G::VE * li;
+
+    Acc acc[CT][G::VE];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int c = 0; c < G::VE; ++c) acc[ct][c] = Acc{0, 0, 0, 0};
+
+    for (int ks = 0; ks < ns; ks += 4 * kUnroll) {
+        T v[kUnroll][G::NV];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int sl = ks + 4 * u + lk;
+#pragma unroll
+            for (int e = 0; e < G::NV; ++e) v[u][e] = (T)0;
+            if (sl < ns && row0 < In) {
+                const int64_t b = s_base[sl];
+                if (CONTIG && row0 + G::VE <= In) {
+                    const T *src = xp + (b + row0) * (CPLX ? 2 : 1);
+                    if (sizeof(T) == 4) {
+                        const float4 q = *(const float4 *)src;
+                        v[u][0] = q.x;
+                        v[u][1] = q.y;
+                        v[u][2] = q.z;
+                        v[u][3] = q.w;
+                    } else {
+                        const double2 q = *(const double2 *)src;
+                        v[u][0] = q.x;
+                        v[u][1] = q.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < G::VE; ++c) {
+                        if (row0 + c < In) {
+                            const int64_t o = b + (int64_t)(row0 + c) * sn;
+                            if (CPLX) {
+                                v[u][2 * c] = xp[2 * o];
+                                v[u][2 * c + 1] = xp[2 * o + 1];
+                            } else {
+                                v[u][c] = xp[o];
+                            }
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int sl = ks + 4 * u + lk;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const T bre = Bre[sl * LDB + ct * 16 + li];
+                if (!CPLX) {
+#pragma unroll
+                    for (int c = 0; c < G::VE; ++c) acc[ct][c] = mfma16(v[u][c], bre, acc[ct][c]);
+                } else {
+                    const T bim = Bim[sl * LDB + ct * 16 + li];
+#pragma unroll
+                    for (int c = 0; c < G::VE; ++c) {
+                        acc[ct][c] = mfma16(v[u][2 * c], bre, acc[ct][c]);
+                        acc[ct][c] = mfma16(v[u][2 * c + 1], bim, acc[ct][c]);
+                    }
+                }
+            }
+        }
+    }
+
+    // Output tile row i' of MFMA c is fiber row rowbase + VE*i' + c.  Lane l
+    // holds column 16*ct + l%16 and tile rows i' = 4*(l/16) + v (FP32
+    // 16x16x4) or i' = l/16 + 4*v (FP64 16x16x4), v = 0..3.
+    T *wp = (T *)a.wpart + (size_t)chunk * a.ncols * In;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int col = ct * 16 + li;
+        if (col >= a.ncols) continue;
+        T *dst = wp + (size_t)col * In;
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv)
+#pragma unroll
+            for (int c = 0; c < G::VE; ++c) {
+                const int ip = sizeof(T) == 8 ? lk + 4 * vv : 4 * lk + vv;
+                const int row = rowbase + G::VE * ip + c;
+                if (row < In) dst[row] = acc[ct][c][vv];
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+GatherPlan plan_gather_bf16(int32_t R, int32_t S, int64_t In, bool contig_ok);
+
+GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_ok) {
+    if (kind == K_BF16) return plan_gather_bf16(R, S, In, contig_ok);
+    GatherPlan g{};
+    g.kind = kind;
+    g.R = R;
+    g.S = S;
+    g.In = (int32_t)In;
+    const bool cplx = (kind == K_C64 || kind == K_C128);
+    const int tsize = (kind == K_F64 || kind == K_C128) ? 8 : 4;
+    g.ncols = cplx ? 2 * R : R;
+    g.ct = (g.ncols + 15) / 16;
+    const int nv = 16 / tsize, ve = cplx ? nv / 2 : nv, rpw = 16 * ve;
+    g.waves = (int)std::min<int64_t>(4, ceil_div(In, rpw));
+    g.rows_wg = g.waves * rpw;
+    g.row_blocks = (int)ceil_div(In, g.rows_wg);
+    // Samples per chunk: grow while the grid keeps >= 2048 workgroups and the
+    // LDS tiles stay within 64 KB (fewer partial products to reduce); shrink
+    // while the grid has < 256 workgroups, never below 16 (the MFMA loop
+    // consumes 16 samples per iteration).
+    const size_t ldb = (size_t)ldb_for(g.ct, tsize);
+    auto lds_for = [&](int k) {
+        const size_t head = (((size_t)k * (16 + 4 * kMaxOrder)) + 15) & ~(size_t)15;
+        return head + (size_t)k * ldb * tsize * 2;  // room for Bre + (Bim or Zraw)
+    };
+    int kc = 64;
+    while (kc < 512 && (int64_t)g.row_blocks * ceil_div(S, 2 * kc) >= 2048 && lds_for(2 * kc) <= 65536) kc *= 2;
+    while (kc > 16 && ((int64_t)g.row_blocks * ceil_div(S, kc) < 256 || lds_for(kc) > 65536)) kc /= 2;
+    g.kc = kc;
+    g.chunks = (int)ceil_div(S, kc);
+    g.contig = contig_ok;
+    g.lds_bytes = lds_for(kc);
+    return g;
+}
+
+template <typename T, bool CPLX, int CT>
+static hipError_t launch_ct(const GatherPlan &gp, const KArgs &k, bool weighted, hipStream_t st) {
+    dim3 grid(gp.row_blocks, gp.chunks), block(64 * gp.waves);
+    if (gp.contig) {
+        if (weighted && !CPLX)
+            hipLaunchKernelGGL((gather_contract<T, CPLX, CT, true, true>), grid, block, gp.lds_bytes, st, k);
+        else
+            hipLaunchKernelGGL((gather_contract<T, CPLX, CT, true, false>), grid, block, gp.lds_bytes, st, k);
+    } else {
+        if (weighted && !CPLX)
+            hipLaunchKernelGGL((gather_contract<T, CPLX, CT, false, true>), grid, block, gp.lds_bytes, st, k);
+        else
+            hipLaunchKernelGGL((gather_contract<T, CPLX, CT, false, false>), grid, block, gp.lds_bytes, st, k);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, bool CPLX>
+static hipError_t launch_t(const GatherPlan &gp, const KArgs &k, bool weighted, hipStream_t st) {
+    switch (gp.ct) {
+        case 1: return launch_ct<T, CPLX, 1>(gp, k, weighted, st);
+        case 2: return launch_ct<T, CPLX, 2>(gp, k, weighted, st);
+        case 3: return launch_ct<T, CPLX, 3>(gp, k, weighted, st);
+        case 4: return launch_ct<T, CPLX, 4>(gp, k, weighted, st);
+        case 5: return launch_ct<T, CPLX, 5>(gp, k, weighted, st);
+        case 6: return launch_ct<T, CPLX, 6>(gp, k, weighted, st);
+        case 7: return launch_ct<T, CPLX, 7>(gp, k, weighted, st);
+        case 8: return launch_ct<T, CPLX, 8>(gp, k, weighted, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bf16_gather(const GatherPlan &gp, const GatherArgs &a, hipStream_t st);
+
+hipError_t launch_gather(const GatherPlan &gp, const GatherArgs &a, hipStream_t st) {
+    if (gp.kind == K_BF16) return launch_bf16_gather(gp, a, st);
+    KArgs k{};
+    k.mi = a.mi;
+    k.X = a.X;
+    k.A = a.A;
+    k.idx = a.idx;
+    k.w = a.w;
+    if (a.cdf) {
+        k.cdf = *a.cdf;
+        k.use_cdf = 1;
+    }
+    k.seed = a.seed;
+    k.t = a.t;
+    k.t_dev = a.t_dev;
+    k.wpart = a.wpart;
+    k.vpart = a.vpart;
+    k.R = gp.R;
+    k.S = gp.S;
+    k.In = gp.In;
+    k.ncols = gp.ncols;
+    k.kc = gp.kc;
+    k.rows_wg = gp.rows_wg;
+    const bool weighted = (a.idx && a.w) || (!a.idx && a.cdf);
+    switch (gp.kind) {
+        case K_F32: return launch_t<float, false>(gp, k, weighted, st);
+        case K_F64: return launch_t<double, false>(gp, k, weighted, st);
+        case K_C64: return launch_t<float, true>(gp, k, false, st);
+        case K_C128: return launch_t<double, true>(gp, k, false, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reduce partials into row-major W and V (real kinds).
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_wv_kernel(const T *wpart, const double *vpart,
+                                                        int32_t chunks, int32_t In, int32_t R,
+                                                        T *W, double *V) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nw = (int64_t)In * R;
+    if (e < nw) {
+        if (!W) return;
+        const int64_t i = e / R, r = e - i * R;
+        double acc = 0.0;
+        for (int c = 0; c < chunks; ++c) acc += (double)wpart[((size_t)c * R + r) * In + i];
+        W[e] = (T)acc;
+    } else if (e < nw + (int64_t)R * R) {
+        const int64_t p = e - nw;
+        double acc = 0.0;
+        for (int c = 0; c < chunks; ++c) acc += vpart[(size_t)c * R * R + p];
+        V[p] = acc;
+    }
+}
+
+// out[e] = sum over p of parts[p * count + e], in order.
+template <typename T>
+__global__ __launch_bounds__(256) void sum_parts_kernel(const T *parts, int32_t np, int64_t count, T *out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double acc = 0.0;
+    for (int p = 0; p < np; ++p) acc += (double)parts[(size_t)p * count + e];
+    out[e] = (T)acc;
+}
+
+hipError_t launch_sum_parts(const void *parts, int32_t np, int64_t count, bool dbl, void *out, hipStream_t st) {
+    const int nb = (int)ceil_div(count, 256);
+    if (dbl)
+        hipLaunchKernelGGL(sum_parts_kernel<double>, dim3(nb), dim3(256), 0, st, (const double *)parts, np, count,
+                           (double *)out);
+    else
+        hipLaunchKernelGGL(sum_parts_kernel<float>, dim3(nb), dim3(256), 0, st, (const float *)parts, np, count,
+                           (float *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_wv(const GatherPlan &gp, const void *wpart, const double *vpart,
+                            void *W, double *V, hipStream_t st) {
+    const int64_t tot = (int64_t)gp.In * gp.R + (int64_t)gp.R * gp.R;
+    const int nb = (int)ceil_div(tot, 256);
+    if (gp.kind == K_F64 || gp.kind == K_C128)
+        hipLaunchKernelGGL(reduce_wv_kernel<double>, dim3(nb), dim3(256), 0, st,
+                           (const double *)wpart, vpart, gp.chunks, gp.In, gp.R, (double *)W, V);
+    else
+        hipLaunchKernelGGL(reduce_wv_kernel<float>, dim3(nb), dim3(256), 0, st,
+                           (const float *)wpart, vpart, gp.chunks, gp.In, gp.R, (float *)W, V);
+    return hipGetLastError();
+}
+
+}  // namespace cprand
