@@ -15,9 +15,17 @@ Also reported (not part of `value`):
     recorded around each pass inside the timed steps,
   - a gather/MTTKRP throughput leg: one cprand_mttkrp_sampled launch over
     many samples of the mixed tensor, timed with HIP events,
-  - the CPU oracle (numpy FP64) on a bounded sample of the same work.
+  - the CPU oracle (numpy FP64) on a bounded sample of the same work,
+  - precision form: 150^4 tensor (R=20, S=1000), BF16 MFMA gathers with one
+    FP32 refinement against the FP32 path, whole decompositions at the paper
+    stop rule, final F-hat of each,
+  - learned proposal: 1000^3 spiky tensor (R=50, congruence 0.9, S=2000);
+    the proposal network is trained on the GPU (100^3 instances, true and
+    initial factors plus ALS iterates), then uniform, CPRAND-MIX, learned and
+    exact-marginal sampling each run one decomposition; final F-hat and the
+    exact fit (evaluated with torch outside the timed runs).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs main,precision,learned]
 """
 import argparse
 import json
@@ -39,7 +47,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--layout", type=int, default=1, help="0: mode-major copies of X-hat, 1: strided gathers")
+    ap.add_argument("--legs", default="main,precision,learned")
+    ap.add_argument("--train-instances", type=int, default=200)
     args = ap.parse_args()
+    legs = set(args.legs.split(","))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -157,7 +168,131 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(X, w, prob, iters / args.steps)
+    del X, Xh, Xv, plan, plan0
+    torch.cuda.empty_cache()
+    if "precision" in legs:
+        out["precision_form"] = precision_leg(P, synth, torch, dev, max(1, args.steps // 2))
+        torch.cuda.empty_cache()
+    if "learned" in legs:
+        out["learned_proposal"] = learned_leg(P, synth, torch, dev, args.train_instances)
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
+
+
+def _timed_runs(plan, Xv, init, reps):
+    """One warm-up decomposition, then `reps` timed ones; returns the last
+    run record and the mean wall time per decomposition."""
+    import torch
+    plan.run(Xv, [M.clone() for M in init])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        A = [M.clone() for M in init]
+        r = plan.run(Xv, A)
+    torch.cuda.synchronize()
+    r["A"] = A
+    return r, (time.perf_counter() - t0) / reps
+
+
+def precision_leg(P, synth, torch, dev, reps):
+    """BF16 tensor copies on MFMA with one FP32 refinement vs the FP32 path,
+    same tensor, seeds and stop rule."""
+    w = synth.WORKLOADS["cprand-150pow4-bf16"]
+    prob = synth.problem_for(w)
+    print("[bench] generating %s" % w.name, flush=True)
+    X = synth.device_tensor(prob, dev, "f32")
+    Xv = P.View(X, w.dims)
+    init = [torch.as_tensor(M, dtype=torch.float32, device=dev) for M in prob.init]
+    res = {}
+    for name, prec in (("fp32", P.PREC_NATIVE), ("bf16_refine", P.PREC_BF16_REFINE)):
+        opts = P.make_opts(w.R, w.S, P_hat=w.P_hat, max_iters=w.max_iters, seed=w.seed, tol=w.tol,
+                           fit_target=w.fit_target, precision=prec, layout=0, use_graph=1)
+        plan = P.Plan(Xv, opts)
+        r, sec = _timed_runs(plan, Xv, init, reps)
+        plan.close()
+        res[name] = {"iters": r["iters"], "s_per_decomposition": sec, "iters_per_s": r["iters"] / sec,
+                     "loop_iters_per_s": r["iters"] / (r["loop_ms"] * 1e-3), "setup_ms": r["setup_ms"],
+                     "final_fit_est": r["fit_est"]}
+        print("[bench] precision %s: %d iters, %.3f s, F-hat %.5f" % (name, r["iters"], sec, r["fit_est"]),
+              flush=True)
+    d = abs(res["bf16_refine"]["final_fit_est"] - res["fp32"]["final_fit_est"])
+    res["workload"] = "150x150x150x150, R=20, congruence 0.5, 1% noise, S=1000, paper stop rule"
+    res["equal_fit"] = d <= 1e-3
+    res["fit_diff"] = d
+    res["speedup_per_decomposition"] = res["fp32"]["s_per_decomposition"] / res["bf16_refine"]["s_per_decomposition"]
+    return res
+
+
+def _exact_fit(torch, X, dims, lam, A):
+    """1 - ||X - [[lam; A]]|| / ||X|| for a 3-way column-major FP32 tensor,
+    in FP64 slabs of the last mode (evaluation only)."""
+    I, J, K = dims
+    A = [M.double() for M in A]
+    lam = lam.double()
+    G = (A[0].T @ A[0]) * (A[1].T @ A[1]) * (A[2].T @ A[2])
+    model_sq = float(lam @ G @ lam)
+    inner, xsq = 0.0, 0.0
+    step = max(1, (1 << 27) // (I * J))
+    for k0 in range(0, K, step):
+        k1 = min(K, k0 + step)
+        slab = X[k0 * I * J:k1 * I * J].double().view(k1 - k0, J, I)       # [k, j, i]
+        xsq += float((slab * slab).sum())
+        T = torch.einsum("kji,ir->kjr", slab, A[0])                           # contract mode 0
+        inner += float(torch.einsum("kjr,jr,kr,r->", T, A[1], A[2][k0:k1], lam))
+    res_sq = max(xsq - 2 * inner + model_sq, 0.0)
+    return 1.0 - (res_sq ** 0.5) / (xsq ** 0.5)
+
+
+def learned_leg(P, synth, torch, dev, n_inst):
+    """Uniform, CPRAND-MIX, learned and exact-marginal sampling on the
+    coherent 1000^3 workload, with the network trained on the GPU first."""
+    from paper_1701_06600_amd.training import proposal_training_set
+    w = synth.WORKLOADS["cprand-1000cube-f32-spiky"]
+    R, S = w.R, w.S
+    print("[bench] training the proposal network on %d instances of 100^3" % n_inst, flush=True)
+    t0 = time.perf_counter()
+    inst = []
+    for k, p in enumerate(synth.training_problems(n_inst, (100, 100, 100), R, w.congruence, w.spiky, w.noise)):
+        Xk = synth.device_tensor(p, dev, "f32")
+        inst.append((P.View(Xk, p.dims), [torch.as_tensor(M, dtype=torch.float32, device=dev) for M in p.factors],
+                     [torch.as_tensor(M, dtype=torch.float32, device=dev) for M in p.init]))
+    Xt, tt, goff = proposal_training_set(inst, R, S)
+    del inst
+    t_build = time.perf_counter() - t0
+    theta = torch.as_tensor(synth.mlp_init(11), dtype=torch.float32, device=dev)
+    t1 = time.perf_counter()
+    epochs = 300
+    hist = P.cprand_mlp_train(theta, Xt, tt, goff, epochs=epochs, lr=3e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    rows = Xt.shape[0]
+    del Xt, tt, goff
+    print("[bench] training: %d rows, loss %.4f -> %.4f, %.1f s" % (rows, hist[0], hist[-1], t_train), flush=True)
+
+    prob = synth.problem_for(w)
+    print("[bench] generating %s" % w.name, flush=True)
+    X = synth.device_tensor(prob, dev, "f32")
+    Xv = P.View(X, w.dims)
+    init = [torch.as_tensor(M, dtype=torch.float32, device=dev) for M in prob.init]
+    res = {"workload": "1000x1000x1000 FP32, R=50, congruence 0.9, 10% rows x20, 1% noise, S=2000, "
+                       "paper stop rule (200 iterations, |dF| <= 1e-4, F >= 0.988)",
+           "training": {"instances": n_inst, "rows": rows, "epochs": epochs, "loss_first": hist[0],
+                        "loss_last": hist[-1], "build_s": t_build, "train_s": t_train}}
+    runs = (("uniform", P.PROPOSAL_UNIFORM, P.MIX_NONE), ("mix", P.PROPOSAL_UNIFORM, P.MIX_FFT),
+            ("learned", P.PROPOSAL_LEARNED, P.MIX_NONE), ("marginal", P.PROPOSAL_MARGINAL, P.MIX_NONE))
+    for name, prop, mix in runs:
+        opts = P.make_opts(R, S, P_hat=w.P_hat, max_iters=w.max_iters, seed=w.seed, tol=w.tol,
+                           fit_target=w.fit_target, mix=mix, proposal=prop, alpha=0.1, layout=1, use_graph=1,
+                           mlp_params=theta if prop == P.PROPOSAL_LEARNED else None)
+        plan = P.Plan(Xv, opts)
+        r, sec = _timed_runs(plan, Xv, init, 1)
+        plan.close()
+        fit = _exact_fit(torch, X, w.dims, r["lambda"], r["A"])
+        res[name] = {"iters": r["iters"], "s_per_decomposition": sec, "iters_per_s": r["iters"] / sec,
+                     "final_fit_est": r["fit_est"], "exact_fit": fit, "fell_back": bool(r["flags"] & P.W_FALLBACK)}
+        print("[bench] %s: %d iters, %.3f s, F-hat %.5f, fit %.5f" % (name, r["iters"], sec, r["fit_est"], fit),
+              flush=True)
+    return res
 
 
 def cpu_baseline(Xdev, w, prob, gpu_iters):

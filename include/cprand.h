@@ -203,6 +203,60 @@ int cprand_layout_copy(const cprand_tensor *X, int32_t n, const cprand_tensor *Y
                        void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Importance proposals for the Khatri-Rao rows of a mode step (a project
+ * addition to the paper's uniform sampling of Section 3.2; the leverage
+ * definitions are those of Section 2.2).
+ *
+ * For the mode step of mode n, with K the other modes, each factor m in K
+ * gets a distribution over its rows: CPRAND_PROPOSAL_MARGINAL uses the exact
+ * marginal of Khatri-Rao leverage, L(i) = a_i^T (G_K^{-1} * prod_{k in K,
+ * k != m} G_k) a_i (G_k = A^(k)T A^(k), G_K their Hadamard product, * =
+ * Hadamard); CPRAND_PROPOSAL_LEARNED uses softmax over rows of a 4-64-64-1
+ * ReLU network (params, cprand_mlp_param_count() floats) applied to the row
+ * features (log f1, log f2, log f3, f4): f1 = I|a_i|^2/|A|_F^2, f2 = (I/R)
+ * a_i^T G_m^{-1} a_i, f3 = (I/R) sum_r a_ir^2/(G_m)_rr, f4 = mean |cosine|
+ * between distinct columns of the other factors in K.  Either is mixed with
+ * uniform, (1-alpha) p + alpha/I, quantised to q_i = max(1, floor(p 2^32))
+ * and written as the table cdf_out[m] (device, I_m + 1 uint64) that
+ * cprand_sample reads.  A: host array of `order` device pointers to float
+ * factors.  workspace: cprand_proposal_workspace_size() bytes.
+ */
+#define CPRAND_PROPOSAL_MARGINAL 3
+#define CPRAND_PROPOSAL_MIXTURE 4  /* reported in proposal_history: fallback, alpha = 0.5 */
+
+int32_t cprand_mlp_param_count(void);
+size_t cprand_proposal_workspace_size(int32_t order, const int64_t *dims, int32_t R);
+int cprand_proposal(int32_t order, const int64_t *dims, int32_t n, int32_t R, const void *const *A,
+                    int32_t kind, const float *params, double alpha, uint64_t *const *cdf_out,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
+/* Training data for the proposal network from one set of factors: for mode
+ * step n, the feature rows (4 floats each) of every factor m != n in
+ * increasing m, and the target distribution of each factor (its exact
+ * Khatri-Rao leverage marginal divided by R).  X_out: device, rows x 4;
+ * t_out: device, rows; rows = sum_{m != n} I_m. */
+int cprand_mlp_features(int32_t order, const int64_t *dims, int32_t n, int32_t R, const void *const *A,
+                        float *X_out, float *t_out, void *workspace, size_t workspace_bytes, void *stream);
+/* logits[i] = network(X[i]) for `rows` feature rows (device). */
+int cprand_mlp_forward(const float *params, const float *X, int64_t rows, float *logits, void *stream);
+/* Gradient (grad, device, param_count floats) of the mean over groups of
+ * the cross-entropy -sum_i t_i log softmax(logits)_i, a group being the rows
+ * group_off[g] .. group_off[g+1]-1 (device int64, ngroups+1 entries, t sums
+ * to 1 within each group); *loss (device) gets the loss, if non-NULL.
+ * workspace: cprand_mlp_workspace_size(rows, ngroups) bytes. */
+size_t cprand_mlp_workspace_size(int64_t rows, int32_t ngroups);
+int cprand_mlp_grad(const float *params, const float *X, const float *t, const int64_t *group_off,
+                    int32_t ngroups, int64_t rows, float *grad, double *loss, void *workspace,
+                    size_t workspace_bytes, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on
+ * params with moment buffers m, v (device, param_count floats each). */
+int cprand_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t step, float lr, void *stream);
+/* epochs x (gradient + Adam) over a fixed training set; loss_history: host,
+ * epochs doubles, or NULL.  Synchronises the stream at the end. */
+int cprand_mlp_train(float *params, const float *X, const float *t, const int64_t *group_off, int32_t ngroups,
+                     int64_t rows, int32_t epochs, float lr, double *loss_history, void *stream);
+
+/* ---------------------------------------------------------------------------
  * The whole decomposition (Alg. 3 / Alg. 4 with the stopping rules of
  * Section 3.4 and Section 4.2).
  */
@@ -227,7 +281,11 @@ typedef struct cprand_opts {
     int32_t patience;     /* stop when the best F has not improved for this many iterations (0 = off) */
     int32_t mix;          /* CPRAND_MIX_* */
     int32_t precision;    /* CPRAND_PREC_* */
-    int32_t proposal;     /* CPRAND_PROPOSAL_* */
+    int32_t proposal;     /* CPRAND_PROPOSAL_*: UNIFORM; TABLE (fixed caller tables); LEARNED or
+                             MARGINAL (recomputed from the current factors at every mode step,
+                             FP32 tensors without mixing; falls back to a half-uniform mixture and
+                             then to uniform sampling when the fit estimate drops by more than
+                             three of its standard deviations below the best, twice in a row) */
     int32_t layout;       /* 0 = mode-major copies where fibers are strided or misaligned, 1 = never copy */
     int32_t use_graph;    /* 1 = replay each outer iteration as a HIP graph */
     double alpha;         /* uniform share of importance proposals */

@@ -18,7 +18,8 @@ import torch
 from . import _abi
 from ._abi import (BF16, C64, C128, EHIP, EINVAL, ENAN, ENOMEM, EUNSUPPORTED, F32, F64, MIX_FFT,
                    MIX_NONE, OK, PREC_BF16, PREC_BF16_REFINE, PREC_NATIVE, PROPOSAL_LEARNED,
-                   PROPOSAL_TABLE, PROPOSAL_UNIFORM, W_FALLBACK, W_MAXIT, W_PINV)
+                   PROPOSAL_MARGINAL, PROPOSAL_MIXTURE, PROPOSAL_TABLE, PROPOSAL_UNIFORM, W_FALLBACK,
+                   W_MAXIT, W_PINV)
 
 _lib = _abi.load()
 
@@ -217,6 +218,73 @@ def mode_major_copy(X, n, dtype=None, ld=None):
     P = math.prod(X.dims) // X.dims[n] * ld
     Y = View(torch.empty(P, dtype=tdt, device=X.data.device), X.dims, strides)
     return cprand_layout_copy(X, n, Y)
+
+
+def cprand_mlp_param_count():
+    return int(_lib.cprand_mlp_param_count())
+
+
+def cprand_proposal(dims, n, R, A, kind, params=None, alpha=0.1, cdf_out=None, ws=None):
+    """Integer proposal tables (list of device uint64 tensors, entry n None)."""
+    order = len(dims)
+    dev = A[(n + 1) % order].device
+    if cdf_out is None:
+        cdf_out = [None if m == n else torch.empty(dims[m] + 1, dtype=torch.uint64, device=dev)
+                   for m in range(order)]
+    cdims = (C.c_int64 * order)(*dims)
+    if ws is None:
+        ws = torch.empty(int(_lib.cprand_proposal_workspace_size(order, cdims, R)), dtype=torch.uint8, device=dev)
+    _check(_lib.cprand_proposal(order, cdims, n, R, _ptr_array([None if m == n else A[m] for m in range(order)], order),
+                                kind, _ptr(params), alpha, _ptr_array(cdf_out, order), _ptr(ws), ws.numel(),
+                                _stream()))
+    return cdf_out
+
+
+def cprand_mlp_features(dims, n, R, A, with_targets=True, ws=None):
+    """Feature rows (rows x 4) and exact-marginal targets for mode step n."""
+    order = len(dims)
+    dev = A[(n + 1) % order].device
+    rows = sum(d for m, d in enumerate(dims) if m != n)
+    X = torch.empty((rows, 4), dtype=torch.float32, device=dev)
+    t = torch.empty(rows, dtype=torch.float32, device=dev) if with_targets else None
+    cdims = (C.c_int64 * order)(*dims)
+    if ws is None:
+        ws = torch.empty(int(_lib.cprand_proposal_workspace_size(order, cdims, R)), dtype=torch.uint8, device=dev)
+    _check(_lib.cprand_mlp_features(order, cdims, n, R, _ptr_array([None if m == n else A[m] for m in range(order)],
+                                                                    order),
+                                    _ptr(X), _ptr(t), _ptr(ws), ws.numel(), _stream()))
+    return X, t
+
+
+def cprand_mlp_forward(params, X):
+    z = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(_lib.cprand_mlp_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(z), _stream()))
+    return z
+
+
+def cprand_mlp_grad(params, X, t, group_off, grad=None, loss=None, ws=None):
+    rows, ng = X.shape[0], group_off.numel() - 1
+    if grad is None:
+        grad = torch.empty_like(params)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=X.device)
+    if ws is None:
+        ws = torch.empty(int(_lib.cprand_mlp_workspace_size(rows, ng)), dtype=torch.uint8, device=X.device)
+    _check(_lib.cprand_mlp_grad(_ptr(params), _ptr(X), _ptr(t), _ptr(group_off), ng, rows, _ptr(grad), _ptr(loss),
+                                _ptr(ws), ws.numel(), _stream()))
+    return grad, loss
+
+
+def cprand_mlp_adam(params, grad, m, v, step, lr=1e-3):
+    _check(_lib.cprand_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, _stream()))
+    return params
+
+
+def cprand_mlp_train(params, X, t, group_off, epochs, lr=1e-3):
+    hist = (C.c_double * epochs)()
+    _check(_lib.cprand_mlp_train(_ptr(params), _ptr(X), _ptr(t), _ptr(group_off), group_off.numel() - 1, X.shape[0],
+                                 epochs, lr, hist, _stream()))
+    return [hist[i] for i in range(epochs)]
 
 
 def make_opts(R, S, P_hat=2 ** 14, max_iters=50, seed=0, tol=0.0, fit_target=2.0, patience=0,

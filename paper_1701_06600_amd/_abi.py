@@ -19,7 +19,7 @@ F64, F32, BF16, C64, C128 = 0, 1, 2, 3, 4
 
 MIX_NONE, MIX_FFT = 0, 1
 PREC_NATIVE, PREC_BF16_REFINE, PREC_BF16 = 0, 1, 2
-PROPOSAL_UNIFORM, PROPOSAL_TABLE, PROPOSAL_LEARNED = 0, 1, 2
+PROPOSAL_UNIFORM, PROPOSAL_TABLE, PROPOSAL_LEARNED, PROPOSAL_MARGINAL, PROPOSAL_MIXTURE = 0, 1, 2, 3, 4
 
 
 class cprand_tensor(C.Structure):
@@ -73,6 +73,20 @@ SIGNATURES = [
                                             C.POINTER(C.c_int64)]),
     ("cprand_layout_copy", C.c_int, [C.POINTER(cprand_tensor), C.c_int32, C.POINTER(cprand_tensor),
                                      C.c_void_p]),
+    ("cprand_mlp_param_count", C.c_int32, []),
+    ("cprand_proposal_workspace_size", C.c_size_t, [C.c_int32, C.POINTER(C.c_int64), C.c_int32]),
+    ("cprand_proposal", C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
+                                  C.c_int32, C.c_void_p, C.c_double, C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t,
+                                  C.c_void_p]),
+    ("cprand_mlp_features", C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("cprand_mlp_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    ("cprand_mlp_workspace_size", C.c_size_t, [C.c_int64, C.c_int32]),
+    ("cprand_mlp_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("cprand_mlp_adam", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_void_p]),
+    ("cprand_mlp_train", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int32,
+                                   C.c_float, C.POINTER(C.c_double), C.c_void_p]),
     ("cprand_plan_create", C.c_int, [C.POINTER(cprand_tensor), C.POINTER(cprand_opts), C.POINTER(C.c_void_p)]),
     ("cprand_plan_run", C.c_int, [C.c_void_p, C.POINTER(cprand_tensor), C.POINTER(C.c_void_p), C.c_void_p,
                                   C.POINTER(cprand_report), C.c_void_p]),

@@ -14,8 +14,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcprand.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["sample.hip", "mttkrp.hip", "mttkrp_bf16.hip", "solve.hip", "fit.hip", "fft.hip",
-           "layout.hip", "api.cpp", "als.cpp"]
+SOURCES = ["sample.hip", "mttkrp.hip", "mttkrp_bf16.hip", "solve.hip", "step.hip", "fit.hip", "fft.hip",
+           "layout.hip", "proposal.hip", "api.cpp", "api_proposal.cpp", "als.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # no packed-FP32 instructions in device code
@@ -38,7 +38,7 @@ def build(verbose=False, jobs=None):
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-Wl,-z,defs", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr[-4000:])

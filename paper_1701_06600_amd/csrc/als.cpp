@@ -78,8 +78,20 @@ struct cprand_plan {
     void *wtmp = nullptr;
     void *ysum = nullptr;
     uint64_t *t_dev = nullptr;
+    unsigned *counter = nullptr;
+    double *hist_mapped = nullptr;  // device address of hist_host
     int32_t *info = nullptr;
     int64_t *seg_off = nullptr;
+    // importance proposals recomputed every mode step (LEARNED / MARGINAL)
+    bool adaptive = false;
+    double *pstats = nullptr, *pH = nullptr, *alpha_dev = nullptr;
+    float *pscore[CPRAND_MAX_ORDER] = {};
+    uint64_t *pcdf[CPRAND_MAX_ORDER] = {};
+    // saved (factors, lambda) states for the proposal fallback: the iterate
+    // with the best fit estimate, the start of a duel, the current proposal's
+    // result in a duel
+    void *snap_fac[3][CPRAND_MAX_ORDER] = {};
+    double *snap_lambda[3] = {};
     std::vector<void *> allocs;
     hipStream_t cap = nullptr;
     hipEvent_t ev[4] = {};
@@ -147,8 +159,11 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         const View &v = p->gview[n];
         const void *vd = view_ptr(p, v, xdata);
-        GatherPlan gp = plan_gather(p->gkind, R, p->o.S, p->dims[n],
-                                    v.data ? true : contig_x[n]);
+        const int64_t In = p->dims[n];
+        // the whole post-gather step in one workgroup when it fits in LDS
+        const bool fused = step_finish_lds((int32_t)In, R, p->mix, p->dbl) <= 156 * 1024;
+        const int maxc = fused ? 8 : 0;
+        GatherPlan gp = plan_gather(p->gkind, R, p->o.S, In, v.data ? true : contig_x[n], maxc);
         GatherArgs ga{};
         ga.mi.order = N;
         ga.mi.n = n;
@@ -162,6 +177,29 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         if (p->o.proposal == CPRAND_PROPOSAL_TABLE) {
             for (int m = 0; m < N; ++m) cdf.p[m] = p->o.proposal_cdf[m];
             ga.cdf = &cdf;
+        } else if (p->adaptive) {
+            // proposals for the factors of this step from their current values
+            const bool learned = p->o.proposal == CPRAND_PROPOSAL_LEARNED;
+            ModeInfo pm{};
+            pm.order = N;
+            pm.n = n;
+            FactorPtrs fp{};
+            for (int m = 0; m < N; ++m) {
+                pm.dims[m] = p->dims[m];
+                pm.strides[m] = 1;
+                fp.p[m] = (m == n) ? nullptr : p->fac[m];
+            }
+            e = launch_mode_stats(fp, pm, R, p->pstats, n, st);
+            if (e == hipSuccess && !learned) e = launch_marginal_h(pm, R, p->pstats, p->pH, st);
+            if (e == hipSuccess)
+                e = launch_row_scores(fp, pm, R, p->pstats, learned ? nullptr : p->pH, p->o.mlp_params, learned,
+                                      p->pscore, nullptr, nullptr, nullptr, st);
+            uint64_t *cd[CPRAND_MAX_ORDER] = {};
+            for (int m = 0; m < N; ++m) cd[m] = (m == n) ? nullptr : p->pcdf[m];
+            if (e == hipSuccess) e = launch_cdf(pm, p->pscore, 0.0, p->alpha_dev, cd, st);
+            if (e != hipSuccess) break;
+            for (int m = 0; m < N; ++m) cdf.p[m] = p->pcdf[m];
+            ga.cdf = &cdf;
         }
         ga.seed = p->o.seed;
         ga.t_dev = p->t_dev;
@@ -171,7 +209,7 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         GatherPlan gr{};
         if (e == hipSuccess && p->refine) {
             const View &rv = p->rview[n];
-            gr = plan_gather(K_F32, R, p->o.S, p->dims[n], rv.data ? true : contig_x[n]);
+            gr = plan_gather(K_F32, R, p->o.S, In, rv.data ? true : contig_x[n], maxc);
             GatherArgs g2 = ga;
             for (int m = 0; m < N; ++m) g2.mi.strides[m] = rv.strides[m];
             g2.X = view_ptr(p, rv, xdata);
@@ -179,7 +217,37 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
             g2.vpart = p->vrpart;
             e = launch_gather(gr, g2, st);
         }
-        const int64_t In = p->dims[n];
+        if (e != hipSuccess) break;
+        if (fused) {
+            StepArgs sa{};
+            sa.In = (int32_t)In;
+            sa.R = R;
+            sa.vpart = p->vpart;
+            sa.vparts = gp.chunks;
+            sa.W = p->wpart;
+            sa.wparts = gp.chunks;
+            sa.wps = (int64_t)gp.ncols * In;
+            sa.wsi = 1;
+            sa.wsr = In;
+            sa.wdouble = p->dbl;
+            sa.mix = p->mix;
+            sa.sign = p->mix ? p->signs + p->seg_off[n] : nullptr;
+            if (p->refine) {
+                sa.Wref = (const float *)p->rpart;
+                sa.wrefparts = gr.chunks;
+                sa.rps = (int64_t)R * In;
+                sa.rsi = 1;
+                sa.rsr = In;
+            }
+            sa.A = p->fac[n];
+            sa.Ahat = p->mix ? p->fhat[n] : nullptr;
+            sa.lambda = p->lambda;
+            sa.info = p->info;
+            FftPlan *fp = nullptr;
+            if (p->mix) fp = fft_plan_get(In, p->dbl, &e);
+            if (e == hipSuccess) e = launch_step_finish(sa, fp, p->dbl, st);
+            continue;
+        }
         SolveArgs sa{};
         sa.In = (int32_t)In;
         sa.R = R;
@@ -188,7 +256,7 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         if (p->mix) {
             const void *y = p->wpart;
             int32_t np = gp.chunks;
-            if (e == hipSuccess && np > 8) {
+            if (np > 8) {
                 e = launch_sum_parts(p->wpart, np, (int64_t)2 * R * In, p->dbl, p->ysum, st);
                 y = p->ysum;
                 np = 1;
@@ -234,7 +302,7 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
     fa.mi.order = N;
     for (int m = 0; m < N; ++m) {
         fa.mi.dims[m] = p->dims[m];
-        fa.mi.strides[m] = p->mix ? 0 : p->xstrides[m];
+        fa.mi.strides[m] = p->xstrides[m];
         fa.A.p[m] = p->mix ? p->fhat[m] : p->fac[m];
     }
     if (p->mix) {
@@ -257,12 +325,14 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
     fa.P_hat = p->o.P_hat;
     fa.seed = p->o.seed;
     fa.part = p->fitpart;
+    fa.counter = p->counter;
+    fa.P = (double)p->P;
+    fa.normX = p->normX;
+    fa.hist = p->hist_dev;
+    fa.hist_host = p->hist_mapped;
+    fa.t_dev = p->t_dev;
     int32_t nb = 0;
-    e = launch_fit_partial(fa, &nb, st);
-    if (e == hipSuccess)
-        e = launch_fit_final(p->fitpart, nb, p->o.P_hat, (double)p->P, p->normX, nullptr, p->hist_dev, p->t_dev, st);
-    if (e == hipSuccess) e = launch_inc_u64(p->t_dev, st);
-    return e;
+    return launch_fit_partial(fa, &nb, st);
 }
 
 }  // namespace
@@ -296,8 +366,14 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
         for (int m = 0; m < X->order; ++m)
             if (!o.proposal_cdf[m]) return set_error(CPRAND_EINVAL, "proposal_cdf[%d] is NULL", m);
         if (o.mix) return set_error(CPRAND_EUNSUPPORTED, "importance sampling with mixing");
+    } else if (o.proposal == CPRAND_PROPOSAL_LEARNED || o.proposal == CPRAND_PROPOSAL_MARGINAL) {
+        if (o.proposal == CPRAND_PROPOSAL_LEARNED && !o.mlp_params)
+            return set_error(CPRAND_EINVAL, "PROPOSAL_LEARNED needs mlp_params");
+        if (xk != K_F32) return set_error(CPRAND_EUNSUPPORTED, "adaptive proposals read FP32 factors");
+        if (o.mix) return set_error(CPRAND_EUNSUPPORTED, "importance sampling with mixing");
+        if (!(o.alpha >= 0.0 && o.alpha <= 1.0)) return set_error(CPRAND_EINVAL, "alpha outside [0, 1]");
     } else if (o.proposal != CPRAND_PROPOSAL_UNIFORM) {
-        return set_error(CPRAND_EUNSUPPORTED, "proposal %d not available in this build", o.proposal);
+        return set_error(CPRAND_EINVAL, "proposal %d", o.proposal);
     }
     if (o.mix && !is_colmajor(X)) return set_error(CPRAND_EUNSUPPORTED, "mixing needs a column-major X");
     cprand_plan *p = new cprand_plan();
@@ -391,13 +467,16 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     size_t wpart = 0, vpart = 0, rpart = 0;
     int64_t maxdim = 1;
     for (int n = 0; n < N; ++n) {
-        GatherPlan gp = plan_gather(p->gkind, R, o.S, p->dims[n], true);
-        const size_t gts = (p->gkind == K_F64 || p->gkind == K_C128) ? 8 : 4;
-        wpart = std::max(wpart, gp.wpart_elems() * gts);
-        vpart = std::max(vpart, gp.vpart_elems() * 8);
-        if (p->refine) {
-            GatherPlan gr = plan_gather(K_F32, R, o.S, p->dims[n], true);
-            rpart = std::max(rpart, gr.wpart_elems() * 4);
+        for (int maxc : {0, 8}) {  // the per-step path and the fused path
+            GatherPlan gp = plan_gather(p->gkind, R, o.S, p->dims[n], true, maxc);
+            const size_t gts = (p->gkind == K_F64 || p->gkind == K_C128) ? 8 : 4;
+            wpart = std::max(wpart, gp.wpart_elems() * gts);
+            vpart = std::max(vpart, gp.vpart_elems() * 8);
+            if (p->refine) {
+                GatherPlan gr = plan_gather(K_F32, R, o.S, p->dims[n], true, maxc);
+                rpart = std::max(rpart, gr.wpart_elems() * 4);
+                vpart = std::max(vpart, gr.vpart_elems() * 8);
+            }
         }
         maxdim = std::max(maxdim, p->dims[n]);
     }
@@ -417,9 +496,27 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     if (e == hipSuccess) e = dalloc(p, (void **)&p->hist_dev, (size_t)o.max_iters * 8);
     if (e == hipSuccess) e = dalloc(p, &p->wtmp, (size_t)maxdim * R * tsz);
     if (e == hipSuccess && p->mix) e = dalloc(p, &p->ysum, (size_t)maxdim * 2 * R * tsz);
+    p->adaptive = o.proposal == CPRAND_PROPOSAL_LEARNED || o.proposal == CPRAND_PROPOSAL_MARGINAL;
+    if (e == hipSuccess && p->adaptive) {
+        e = dalloc(p, (void **)&p->pstats, (size_t)N * mode_stats_doubles(R) * 8);
+        if (e == hipSuccess) e = dalloc(p, (void **)&p->pH, (size_t)N * R * R * 8);
+        for (int m = 0; m < N && e == hipSuccess; ++m) {
+            e = dalloc(p, (void **)&p->pscore[m], (size_t)p->dims[m] * 4);
+            if (e == hipSuccess) e = dalloc(p, (void **)&p->pcdf[m], (size_t)(p->dims[m] + 1) * 8);
+        }
+        if (e == hipSuccess) e = dalloc(p, (void **)&p->alpha_dev, 8);
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+            for (int m = 0; m < N && e == hipSuccess; ++m)
+                e = dalloc(p, &p->snap_fac[k][m], (size_t)p->dims[m] * R * tsz);
+            if (e == hipSuccess) e = dalloc(p, (void **)&p->snap_lambda[k], (size_t)R * 8);
+        }
+    }
     if (e == hipSuccess) e = dalloc(p, (void **)&p->t_dev, 8);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->counter, 8);
     if (e == hipSuccess) e = dalloc(p, (void **)&p->info, 8);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&p->hist_host, (size_t)o.max_iters * 8, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&p->hist_host, (size_t)o.max_iters * 8, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&p->hist_mapped, p->hist_host, 0);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&p->ev[i]);
     for (int i = 0; i < 2 + 4 * CPRAND_MAX_ORDER && e == hipSuccess; ++i) e = hipEventCreate(&p->tev[i]);
@@ -466,6 +563,12 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
         e = hipMemcpyAsync(p->fac[m], A_inout[m], (size_t)p->dims[m] * R * tsz, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = launch_fill_u64(p->t_dev, 0, st);
     if (e == hipSuccess) e = launch_fill_u64((uint64_t *)p->info, 0, st);
+    if (e == hipSuccess) e = launch_fill_u64((uint64_t *)p->counter, 0, st);
+    if (e == hipSuccess && p->adaptive) {
+        uint64_t bits;
+        memcpy(&bits, &p->o.alpha, 8);
+        e = launch_fill_u64((uint64_t *)p->alpha_dev, bits, st);
+    }
     ModeInfo xi = mode_info(X, 0);
     bool timed_mix[CPRAND_MAX_ORDER] = {}, timed_lay[CPRAND_MAX_ORDER] = {};
     hipEvent_t *tev = p->tev;
@@ -544,17 +647,103 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
     Stop stop(p->o);
     int it = 0;
     double F = 0.0;
+    // Adaptive proposals fall back learned -> mixture (alpha 0.5) -> uniform
+    // (alpha 1, which reproduces uniform sampling exactly) when the sampled
+    // fit estimate judges the current proposal worse, by either of two tests.
+    //  - Duel: at t = 1, 3, 7, 15, ... one outer iteration is run with the
+    //    current proposal and, from the same factors and with the same random
+    //    counters, with uniform sampling; uniform sampling wins when its F-hat
+    //    is higher by three standard deviations of the estimate,
+    //    (1 - F)/sqrt(2 P-hat), and its residual 1 - F-hat is less than half.
+    //    The winner's iterate is kept.
+    //  - Decline: F-hat below the best so far by more than both three standard
+    //    deviations and half the best residual, twice in a row; the proposal
+    //    steps down one level and the run resumes from the factors of the best
+    //    iterate.
+    // The margins are wide because sampled ALS is not monotone: a good
+    // proposal moves F-hat by up to about a third of the residual between
+    // iterations.
+    enum { SNAP_BEST = 0, SNAP_PRE = 1, SNAP_CUR = 2 };
+    auto save = [&](int k) {
+        hipError_t r = hipSuccess;
+        for (int m = 0; m < N && r == hipSuccess; ++m)
+            r = hipMemcpyAsync(p->snap_fac[k][m], p->fac[m], (size_t)p->dims[m] * R * tsz, hipMemcpyDeviceToDevice,
+                               st);
+        if (r == hipSuccess) r = hipMemcpyAsync(p->snap_lambda[k], p->lambda, (size_t)R * 8, hipMemcpyDeviceToDevice, st);
+        return r;
+    };
+    auto load = [&](int k) {
+        hipError_t r = hipSuccess;
+        for (int m = 0; m < N && r == hipSuccess; ++m)
+            r = hipMemcpyAsync(p->fac[m], p->snap_fac[k][m], (size_t)p->dims[m] * R * tsz, hipMemcpyDeviceToDevice,
+                               st);
+        if (r == hipSuccess) r = hipMemcpyAsync(p->lambda, p->snap_lambda[k], (size_t)R * 8, hipMemcpyDeviceToDevice, st);
+        return r;
+    };
+    auto level_alpha = [&](int l) { return l == 0 ? p->o.alpha : (l == 1 ? 0.5 : 1.0); };
+    auto set_alpha = [&](double a) {
+        uint64_t bits;
+        memcpy(&bits, &a, 8);
+        return launch_fill_u64((uint64_t *)p->alpha_dev, bits, st);
+    };
+    auto run_iteration = [&]() {
+        hipError_t r = exec ? hipGraphLaunch(exec, st) : enqueue_iteration(p, X->data, contig_x, st);
+        if (r == hipSuccess) r = hipEventRecord(p->ev[2], st);
+        if (r == hipSuccess) r = hipEventSynchronize(p->ev[2]);
+        return r;
+    };
+    int level = 0, worse = 0, fell_back = 0;
+    double best = -INFINITY;
+    std::vector<int> levels;
     for (; it < p->o.max_iters; ++it) {
-        e = exec ? hipGraphLaunch(exec, st) : enqueue_iteration(p, X->data, contig_x, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(p->hist_host + it, p->hist_dev + it, 8, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipEventRecord(p->ev[2], st);
-        if (e == hipSuccess) e = hipEventSynchronize(p->ev[2]);
+        const bool duel = p->adaptive && level < 2 && it > 0 && ((it + 1) & it) == 0;
+        if (duel) e = save(SNAP_PRE);
+        if (e == hipSuccess) e = run_iteration();
         if (e != hipSuccess) break;
         F = p->hist_host[it];
+        if (duel && isfinite(F)) {
+            const double F1 = F;
+            e = save(SNAP_CUR);
+            if (e == hipSuccess) e = load(SNAP_PRE);
+            if (e == hipSuccess) e = set_alpha(level_alpha(2));
+            if (e == hipSuccess) e = launch_fill_u64(p->t_dev, (uint64_t)it, st);
+            if (e == hipSuccess) e = run_iteration();
+            if (e != hipSuccess) break;
+            const double F2 = p->hist_host[it];
+            const double sigma = (1.0 - F1) / sqrt(2.0 * p->o.P_hat);
+            if (isfinite(F2) && F2 > F1 + 3.0 * sigma && (1.0 - F2) < 0.5 * (1.0 - F1)) {
+                level = 2;
+                worse = 0;
+                fell_back = 1;
+                F = F2;
+            } else {
+                e = load(SNAP_CUR);
+                if (e == hipSuccess) e = set_alpha(level_alpha(level));
+                p->hist_host[it] = F1;
+                F = F1;
+            }
+        }
         if (!isfinite(F)) {
             e = hipErrorUnknown;
             break;
         }
+        levels.push_back(level);
+        if (p->adaptive && e == hipSuccess) {
+            const double sigma = (1.0 - F) / sqrt(2.0 * p->o.P_hat);
+            worse = (F < best - fmax(3.0 * sigma, 0.5 * (1.0 - best))) ? worse + 1 : 0;
+            if (F > best) {
+                best = F;
+                e = save(SNAP_BEST);
+            }
+            if (e == hipSuccess && worse >= 2 && level < 2) {
+                ++level;
+                worse = 0;
+                fell_back = 1;
+                e = set_alpha(level_alpha(level));
+                if (e == hipSuccess) e = load(SNAP_BEST);
+            }
+        }
+        if (e != hipSuccess) break;
         if (stop(it, F)) {
             ++it;
             break;
@@ -573,6 +762,7 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "results");
     int flags = info ? CPRAND_W_PINV : 0;
+    if (fell_back) flags |= CPRAND_W_FALLBACK;
     if (it >= p->o.max_iters) flags |= CPRAND_W_MAXIT;
     if (rep) {
         rep->iters = it;
@@ -596,7 +786,11 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
         }
         if (rep->fit_history) memcpy(rep->fit_history, p->hist_host, (size_t)it * 8);
         if (rep->proposal_history)
-            for (int i = 0; i < it; ++i) rep->proposal_history[i] = p->o.proposal;
+            for (int i = 0; i < it; ++i) {
+                const int lv = i < (int)levels.size() ? levels[i] : 0;
+                rep->proposal_history[i] =
+                    lv == 0 ? p->o.proposal : (lv == 1 ? CPRAND_PROPOSAL_MIXTURE : CPRAND_PROPOSAL_UNIFORM);
+            }
     }
     return flags;
 }

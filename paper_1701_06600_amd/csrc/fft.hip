@@ -4,13 +4,19 @@
 //
 // The transform is the Stockham autosort formulation (Govindaraju et al.,
 // "High performance discrete Fourier transforms on graphics processors",
-// SC'08) on a tile of TC fibers held in LDS: stage s with radix r reads
-// element j + t*L/r (t < r), applies the twiddle exp(+-2 pi i t k/(Ns r)),
-// k = j mod Ns, does an r-point DFT and writes element (j/Ns)*Ns*r + k + t*Ns;
-// two LDS buffers alternate between stages.  Radices 2, 3, 4, 5, 7.
-// Twiddles exp(-2 pi i q/L) are computed on the host in FP64 and uploaded.
-// Strided modes move whole rows of TC neighbouring fibers (contiguous in
-// memory), so reads and writes stay coalesced without a transpose.
+// SC'08) applied to a tile of TC fibers held in LDS as [L][TC+1] complex:
+// stage s with radix r takes elements j + t*L/r (t < r), multiplies by the
+// twiddle exp(+-2 pi i t k/(Ns r)) with k = j mod Ns, does an r-point DFT and
+// stores element (j/Ns)*Ns*r + k + t*Ns.  Twiddles exp(-2 pi i q/L) are
+// computed on the host in FP64 and uploaded; kernels copy them to LDS.
+//
+// Tensor passes use a compile-time radix schedule for the common lengths:
+// every stage reads its butterfly inputs into registers, synchronises and
+// writes the outputs back in place, so one LDS tile suffices and all
+// register indexing is static.  Other {2,3,5,7}-smooth lengths use a generic
+// path with two LDS tiles.  Strided modes move rows of TC neighbouring
+// fibers (TC*8 contiguous bytes), so reads and writes stay coalesced without
+// a transpose.
 #include <math.h>
 
 #include <map>
@@ -19,182 +25,162 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "fft_device.hpp"
 
 namespace cprand {
 
-template <typename T>
-struct cx {
-    T re, im;
-};
-template <typename T>
-__device__ inline cx<T> cmul(cx<T> a, cx<T> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-template <typename T>
-__device__ inline cx<T> cadd(cx<T> a, cx<T> b) {
-    return {a.re + b.re, a.im + b.im};
-}
-template <typename T>
-__device__ inline cx<T> csub(cx<T> a, cx<T> b) {
-    return {a.re - b.re, a.im - b.im};
-}
-template <typename T>
-__device__ inline cx<T> cscale(cx<T> a, T s) {
-    return {a.re * s, a.im * s};
-}
-// multiply by i*dir
-template <typename T>
-__device__ inline cx<T> cmul_idir(cx<T> a, int dir) {
-    return dir > 0 ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
-}
-
-struct FftPlan {
-    int64_t L;
-    int nrad;
-    int rad[24];
-    void *tw;  // device, L complex (float or double): exp(-2 pi i q / L)
-};
-
-// r-point DFT in place, sign dir (-1 forward, +1 inverse).
-template <typename T, int R>
-__device__ inline void small_dft(cx<T> *v, int dir, const cx<T> *tw, int64_t L) {
-    if (R == 2) {
-        cx<T> a = v[0], b = v[1];
-        v[0] = cadd(a, b);
-        v[1] = csub(a, b);
-    } else if (R == 3) {
-        const T h = (T)0.86602540378443864676;  // sqrt(3)/2
-        cx<T> a = v[0], b = v[1], c = v[2];
-        cx<T> s = cadd(b, c), d = csub(b, c);
-        cx<T> m = csub(a, cscale(s, (T)0.5));
-        cx<T> q = cmul_idir(cscale(d, h), dir);
-        v[0] = cadd(a, s);
-        v[1] = cadd(m, q);
-        v[2] = csub(m, q);
-    } else if (R == 4) {
-        cx<T> a = v[0], b = v[1], c = v[2], d = v[3];
-        cx<T> s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d), d1 = cmul_idir(csub(b, d), dir);
-        v[0] = cadd(s0, s1);
-        v[1] = cadd(d0, d1);
-        v[2] = csub(s0, s1);
-        v[3] = csub(d0, d1);
-    } else if (R == 5) {
-        const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
-        const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
-        cx<T> x0 = v[0];
-        cx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-        cx<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-        cx<T> a1 = cadd(x0, cadd(cscale(t1, c1), cscale(t2, c2)));
-        cx<T> a2 = cadd(x0, cadd(cscale(t1, c2), cscale(t2, c1)));
-        cx<T> b1 = cmul_idir(cadd(cscale(t3, s1), cscale(t4, s2)), dir);
-        cx<T> b2 = cmul_idir(csub(cscale(t3, s2), cscale(t4, s1)), dir);
-        v[0] = cadd(x0, cadd(t1, t2));
-        v[1] = cadd(a1, b1);
-        v[4] = csub(a1, b1);
-        v[2] = cadd(a2, b2);
-        v[3] = csub(a2, b2);
-    } else {
-        // direct R-point DFT with the length-L table: w^(a b) = tw[(a b mod R) L/R]
-        cx<T> out[R];
-        const int64_t step = L / R;
-        for (int a = 0; a < R; ++a) {
-            cx<T> acc = v[0];
-            for (int b = 1; b < R; ++b) {
-                cx<T> w = tw[((a * b) % R) * step];
-                if (dir > 0) w.im = -w.im;
-                acc = cadd(acc, cmul(v[b], w));
+// Tensor pass along mode m.  The tensor is [J][L][K] (J = product of the
+// dims before m, K after); flattened column q of the J*K fibers is fiber
+// (j = q % J, k = q / J) with element l at j + J*L*k + J*l.  FIRST: read the
+// real input, apply the product of all sign vectors, write complex.
+// VEC: 16-byte global accesses (4 real inputs along a contiguous fiber in
+// the first pass; 2 neighbouring complex fibers per row in strided passes,
+// where every tile lies inside one k and starts 16-byte aligned).
+template <typename Tin, int L, int TC, int NT, bool FIRST, bool VEC>
+__global__ __launch_bounds__(NT) void mix_pass_ct(const Tin *X, cx<float> *Xh, int64_t J, int64_t K, ModeInfo xi,
+                                                  int m, const int8_t *signs, const cx<float> *twg) {
+    constexpr int LDT = TC + 1;
+    __shared__ cx<float> buf[L * LDT];
+    __shared__ cx<float> tw[L];
+    __shared__ int64_t cbase[TC];
+    __shared__ float csign[TC];
+    const int tid = threadIdx.x;
+    const int64_t ncols = J * K;
+    const int64_t q0 = (int64_t)blockIdx.x * TC;
+    const int nc = (int)min((int64_t)TC, ncols - q0);
+    for (int e = tid; e < L; e += NT) tw[e] = twg[e];
+    int moff = 0;
+    if (FIRST)
+        for (int mm = 0; mm < m; ++mm) moff += (int)xi.dims[mm];
+    for (int c = tid; c < TC; c += NT) {
+        if (c < nc) {
+            const int64_t q = q0 + c;
+            int64_t j = q % J, k = q / J;
+            cbase[c] = j + J * L * k;
+            if (FIRST) {
+                float sg = 1.0f;
+                int off = 0;
+                for (int mm = 0; mm < xi.order; ++mm) {
+                    if (mm != m) {
+                        int64_t im;
+                        if (mm < m) {
+                            im = j % xi.dims[mm];
+                            j /= xi.dims[mm];
+                        } else {
+                            im = k % xi.dims[mm];
+                            k /= xi.dims[mm];
+                        }
+                        sg *= (float)signs[off + im];
+                    }
+                    off += (int)xi.dims[mm];
+                }
+                csign[c] = sg;
             }
-            out[a] = acc;
         }
-        for (int a = 0; a < R; ++a) v[a] = out[a];
+    }
+    __syncthreads();
+    const float scale = (float)(1.0 / sqrt((double)L));
+    if (VEC && FIRST) {
+        static_assert(L % 4 == 0 || !VEC || !FIRST, "vector first pass needs L % 4 == 0");
+        for (int e = tid; e < L * TC / 4; e += NT) {
+            const int c = e / (L / 4), l4 = (e - c * (L / 4)) * 4;
+            float4 v = {0.f, 0.f, 0.f, 0.f};
+            if (c < nc) v = *(const float4 *)((const float *)X + cbase[c] + l4);
+            const float sc = c < nc ? csign[c] : 0.f;
+            buf[(l4 + 0) * LDT + c] = {v.x * sc * (float)signs[moff + l4 + 0], 0.f};
+            buf[(l4 + 1) * LDT + c] = {v.y * sc * (float)signs[moff + l4 + 1], 0.f};
+            buf[(l4 + 2) * LDT + c] = {v.z * sc * (float)signs[moff + l4 + 2], 0.f};
+            buf[(l4 + 3) * LDT + c] = {v.w * sc * (float)signs[moff + l4 + 3], 0.f};
+        }
+    } else if (VEC) {
+        for (int e = tid; e < L * TC / 2; e += NT) {
+            const int l = e / (TC / 2), c = (e - l * (TC / 2)) * 2;
+            float4 v = {0.f, 0.f, 0.f, 0.f};
+            if (c < nc) v = *(const float4 *)(Xh + cbase[c] + J * (int64_t)l);
+            buf[l * LDT + c] = {v.x, v.y};
+            buf[l * LDT + c + 1] = {v.z, v.w};
+        }
+    } else {
+        for (int e = tid; e < L * TC; e += NT) {
+            int l, c;
+            if (J == 1) {
+                c = e / L;
+                l = e - c * L;
+            } else {
+                l = e / TC;
+                c = e - l * TC;
+            }
+            cx<float> v = {0.f, 0.f};
+            if (c < nc) {
+                const int64_t o = cbase[c] + J * (int64_t)l;
+                if (FIRST) {
+                    v.re = (float)X[o] * csign[c] * (float)signs[moff + l];
+                } else {
+                    v = Xh[o];
+                }
+            }
+            buf[l * LDT + c] = v;
+        }
+    }
+    __syncthreads();
+    fft_ct<float, L, TC, NT, -1>(buf, tw);
+    if (VEC && FIRST) {
+        for (int e = tid; e < L * TC / 2; e += NT) {
+            const int c = e / (L / 2), l2 = (e - c * (L / 2)) * 2;
+            if (c < nc) {
+                const cx<float> a = buf[l2 * LDT + c], b = buf[(l2 + 1) * LDT + c];
+                *(float4 *)(Xh + cbase[c] + l2) = {a.re * scale, a.im * scale, b.re * scale, b.im * scale};
+            }
+        }
+        return;
+    }
+    if (VEC) {
+        for (int e = tid; e < L * TC / 2; e += NT) {
+            const int l = e / (TC / 2), c = (e - l * (TC / 2)) * 2;
+            if (c < nc) {
+                const cx<float> a = buf[l * LDT + c], b = buf[l * LDT + c + 1];
+                *(float4 *)(Xh + cbase[c] + J * (int64_t)l) = {a.re * scale, a.im * scale, b.re * scale, b.im * scale};
+            }
+        }
+        return;
+    }
+    for (int e = tid; e < L * TC; e += NT) {
+        int l, c;
+        if (J == 1) {
+            c = e / L;
+            l = e - c * L;
+        } else {
+            l = e / TC;
+            c = e - l * TC;
+        }
+        if (c < nc) Xh[cbase[c] + J * (int64_t)l] = cscale(buf[l * LDT + c], scale);
     }
 }
 
-// One Stockham stage over TC columns: in/out are [L][ldt] column tiles.
-template <typename T, int R>
-__device__ inline void stage(const cx<T> *in, cx<T> *out, int64_t L, int ldt, int tc, int64_t Ns,
-                             int dir, const cx<T> *tw) {
-    const int64_t nb = (L / R) * tc;
-    const int64_t twstep = L / (Ns * R);
-    for (int64_t id = threadIdx.x; id < nb; id += blockDim.x) {
-        const int col = (int)(id % tc);
-        const int64_t j = id / tc;
-        const int64_t k = j % Ns;
-        cx<T> v[R];
-#pragma unroll
-        for (int t = 0; t < R; ++t) v[t] = in[(j + t * (L / R)) * ldt + col];
-#pragma unroll
-        for (int t = 1; t < R; ++t) {
-            cx<T> w = tw[t * k * twstep];
-            if (dir > 0) w.im = -w.im;
-            v[t] = cmul(v[t], w);
-        }
-        small_dft<T, R>(v, dir, tw, L);
-        const int64_t o = (j / Ns) * Ns * R + k;
-#pragma unroll
-        for (int t = 0; t < R; ++t) out[(o + t * Ns) * ldt + col] = v[t];
-    }
-}
-
-// Transform the tile in buf0 (result may end in buf0 or buf1; returned).
-template <typename T>
-__device__ cx<T> *fft_tile(cx<T> *buf0, cx<T> *buf1, const FftPlan &fp, int ldt, int tc, int dir,
-                           const cx<T> *tw) {
-    cx<T> *in = buf0, *out = buf1;
-    int64_t Ns = 1;
-    for (int s = 0; s < fp.nrad; ++s) {
-        const int r = fp.rad[s];
-        switch (r) {
-            case 2: stage<T, 2>(in, out, fp.L, ldt, tc, Ns, dir, tw); break;
-            case 3: stage<T, 3>(in, out, fp.L, ldt, tc, Ns, dir, tw); break;
-            case 4: stage<T, 4>(in, out, fp.L, ldt, tc, Ns, dir, tw); break;
-            case 5: stage<T, 5>(in, out, fp.L, ldt, tc, Ns, dir, tw); break;
-            default: stage<T, 7>(in, out, fp.L, ldt, tc, Ns, dir, tw); break;
-        }
-        __syncthreads();
-        Ns *= r;
-        cx<T> *tmp = in;
-        in = out;
-        out = tmp;
-    }
-    return in;
-}
-
-// Columns per tile: two LDS buffers of L x (tc+1) complex within ~64 KB.
-static int tile_cols(int64_t L, int esz) {
-    int64_t tc = (int64_t)(65536 / (2 * esz)) / L - 1;
-    if (tc > 16) tc = 16;
-    if (tc < 1) tc = 1;
-    return (int)tc;
-}
-
-// ---------------------------------------------------------------------------
-// Tensor pass along mode m (J = prod of dims before m, K = after; column q
-// of the flattened (j, k) range is fiber (j, k), element l at
-// j + J*(l + L*k)).
+// Generic tensor pass (any {2,3,5,7}-smooth length, float or double).
 template <typename T, typename Tin>
-__global__ __launch_bounds__(256) void mix_pass_kernel(FftPlan fp, const Tin *X, cx<T> *Xh, int64_t J,
-                                                       int64_t K, int tc, int first, ModeInfo xi,
-                                                       int m, const int8_t *signs,
-                                                       double *normsq_part) {
+__global__ __launch_bounds__(256) void mix_pass_rt(FftPlan fp, const Tin *X, cx<T> *Xh, int64_t J, int64_t K,
+                                                   int tc, int first, ModeInfo xi, int m, const int8_t *signs) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const int64_t L = fp.L;
+    const int L = (int)fp.L;
     const int ldt = tc + 1;
     cx<T> *b0 = (cx<T> *)lds, *b1 = b0 + L * ldt;
-    const cx<T> *tw = (const cx<T> *)fp.tw;
-    __shared__ double sh[256 / kWave];
-    __shared__ double s_colsign[16];
+    cx<T> *tw = b1 + L * ldt;
+    __shared__ int64_t cbase[16];
+    __shared__ double csign[16];
     const int64_t ncols = J * K;
     const int64_t q0 = (int64_t)blockIdx.x * tc;
     const int nc = (int)min((int64_t)tc, ncols - q0);
-
-    // sign product of every mode except m for each column (first pass);
-    // signs are stored mode after mode
-    if (first) {
-        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-            int64_t j = (q0 + c) % J, k = (q0 + c) / J;
+    for (int e = threadIdx.x; e < L; e += blockDim.x) tw[e] = ((const cx<T> *)fp.tw)[e];
+    int moff = 0;
+    for (int mm = 0; mm < m; ++mm) moff += (int)xi.dims[mm];
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        const int64_t q = q0 + c;
+        int64_t j = q % J, k = q / J;
+        cbase[c] = j + J * L * k;
+        if (first) {
             double sg = 1.0;
-            int64_t off = 0;
+            int off = 0;
             for (int mm = 0; mm < xi.order; ++mm) {
                 if (mm != m) {
                     int64_t im;
@@ -207,18 +193,14 @@ __global__ __launch_bounds__(256) void mix_pass_kernel(FftPlan fp, const Tin *X,
                     }
                     sg *= (double)signs[off + im];
                 }
-                off += xi.dims[mm];
+                off += (int)xi.dims[mm];
             }
-            s_colsign[c] = sg;
+            csign[c] = sg;
         }
     }
-    int64_t moff = 0;
-    for (int mm = 0; mm < m; ++mm) moff += xi.dims[mm];
     __syncthreads();
-    double acc = 0.0;
-    // load
-    for (int64_t e = threadIdx.x; e < L * tc; e += blockDim.x) {
-        int64_t l, c;
+    for (int e = threadIdx.x; e < L * tc; e += blockDim.x) {
+        int l, c;
         if (J == 1) {
             c = e / L;
             l = e - c * L;
@@ -228,28 +210,19 @@ __global__ __launch_bounds__(256) void mix_pass_kernel(FftPlan fp, const Tin *X,
         }
         cx<T> v = {(T)0, (T)0};
         if (c < nc) {
-            const int64_t q = q0 + c;
-            const int64_t j = q % J, k = q / J;
-            const int64_t o = j + J * (l + L * k);
-            if (first) {
-                const double x = (double)X[o];
-                acc += x * x;
-                v.re = (T)(x * s_colsign[c] * (double)signs[moff + l]);
-            } else {
+            const int64_t o = cbase[c] + J * (int64_t)l;
+            if (first)
+                v.re = (T)((double)X[o] * csign[c] * (double)signs[moff + l]);
+            else
                 v = Xh[o];
-            }
         }
         b0[l * ldt + c] = v;
     }
-    if (first && normsq_part) {
-        const double s = block_sum<256>(acc, sh);
-        if (threadIdx.x == 0) normsq_part[blockIdx.x] = s;
-    }
     __syncthreads();
-    cx<T> *res = fft_tile<T>(b0, b1, fp, ldt, tc, -1, tw);
+    cx<T> *res = fft_tile_rt<T, -1>(b0, b1, fp, ldt, tc, tw);
     const T scale = (T)(1.0 / sqrt((double)L));
-    for (int64_t e = threadIdx.x; e < L * tc; e += blockDim.x) {
-        int64_t l, c;
+    for (int e = threadIdx.x; e < L * tc; e += blockDim.x) {
+        int l, c;
         if (J == 1) {
             c = e / L;
             l = e - c * L;
@@ -257,34 +230,40 @@ __global__ __launch_bounds__(256) void mix_pass_kernel(FftPlan fp, const Tin *X,
             l = e / tc;
             c = e - l * tc;
         }
-        if (c < nc) {
-            const int64_t q = q0 + c;
-            const int64_t j = q % J, k = q / J;
-            Xh[j + J * (l + L * k)] = cscale(res[l * ldt + c], scale);
-        }
+        if (c < nc) Xh[cbase[c] + J * (int64_t)l] = cscale(res[l * ldt + c], scale);
     }
 }
 
+// Columns per tile of the generic path: two tiles + twiddles within ~64 KB.
+static int tile_cols(int64_t L, int esz) {
+    int64_t tc = (int64_t)(65536 / esz - L) / (2 * L) - 1;
+    if (tc > 16) tc = 16;
+    if (tc < 1) tc = 1;
+    return (int)tc;
+}
+static size_t tile_lds(int64_t L, int tc, size_t esz) { return (2 * (size_t)L * (tc + 1) + (size_t)L) * esz; }
 
 // ---------------------------------------------------------------------------
 // Factor mix (A-hat = F D A), inverse factor mix (A = Re(D F^* A-hat)) and
 // the unmix of a mode step (W = D Re(F^* Y)).  Columns of an I x R
 // row-major matrix are the transformed fibers.
 template <typename T>
-__global__ __launch_bounds__(256) void factor_mix_kernel(FftPlan fp, const T *in, const int8_t *sign,
-                                                         T *out, int R, int tc, int inverse) {
+__global__ __launch_bounds__(256) void factor_mix_kernel(FftPlan fp, const T *in, const int8_t *sign, T *out, int R,
+                                                         int tc, int inverse) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const int64_t L = fp.L;
+    const int L = (int)fp.L;
     const int ldt = tc + 1;
     cx<T> *b0 = (cx<T> *)lds, *b1 = b0 + L * ldt;
+    cx<T> *tw = b1 + L * ldt;
+    for (int e = threadIdx.x; e < L; e += blockDim.x) tw[e] = ((const cx<T> *)fp.tw)[e];
     const int r0 = blockIdx.x * tc;
     const int nc = min(tc, R - r0);
-    for (int64_t e = threadIdx.x; e < L * tc; e += blockDim.x) {
-        const int64_t l = e / tc;
-        const int c = (int)(e - l * tc);
+    for (int e = threadIdx.x; e < L * tc; e += blockDim.x) {
+        const int l = e / tc;
+        const int c = e - l * tc;
         cx<T> v = {(T)0, (T)0};
         if (c < nc) {
-            const int64_t o = l * R + r0 + c;
+            const int64_t o = (int64_t)l * R + r0 + c;
             if (!inverse)
                 v.re = (T)sign[l] * in[o];
             else
@@ -293,13 +272,13 @@ __global__ __launch_bounds__(256) void factor_mix_kernel(FftPlan fp, const T *in
         b0[l * ldt + c] = v;
     }
     __syncthreads();
-    cx<T> *res = fft_tile<T>(b0, b1, fp, ldt, tc, inverse ? 1 : -1, (const cx<T> *)fp.tw);
+    cx<T> *res = inverse ? fft_tile_rt<T, 1>(b0, b1, fp, ldt, tc, tw) : fft_tile_rt<T, -1>(b0, b1, fp, ldt, tc, tw);
     const T scale = (T)(1.0 / sqrt((double)L));
-    for (int64_t e = threadIdx.x; e < L * tc; e += blockDim.x) {
-        const int64_t l = e / tc;
-        const int c = (int)(e - l * tc);
+    for (int e = threadIdx.x; e < L * tc; e += blockDim.x) {
+        const int l = e / tc;
+        const int c = e - l * tc;
         if (c >= nc) continue;
-        const int64_t o = l * R + r0 + c;
+        const int64_t o = (int64_t)l * R + r0 + c;
         const cx<T> v = res[l * ldt + c];
         if (!inverse) {
             out[2 * o] = v.re * scale;
@@ -311,18 +290,20 @@ __global__ __launch_bounds__(256) void factor_mix_kernel(FftPlan fp, const T *in
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void unmix_kernel(FftPlan fp, const T *ypart, int chunks, int R,
-                                                    const int8_t *sign, T *W, int rowmajor, int tc) {
+__global__ __launch_bounds__(256) void unmix_kernel(FftPlan fp, const T *ypart, int chunks, int R, const int8_t *sign,
+                                                    T *W, int rowmajor, int tc) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const int64_t L = fp.L;
+    const int L = (int)fp.L;
     const int ldt = tc + 1;
     cx<T> *b0 = (cx<T> *)lds, *b1 = b0 + L * ldt;
+    cx<T> *tw = b1 + L * ldt;
+    for (int e = threadIdx.x; e < L; e += blockDim.x) tw[e] = ((const cx<T> *)fp.tw)[e];
     const int r0 = blockIdx.x * tc;
     const int nc = min(tc, R - r0);
     const size_t cstride = (size_t)2 * R * L;
-    for (int64_t e = threadIdx.x; e < L * tc; e += blockDim.x) {
-        const int c = (int)(e / L);
-        const int64_t l = e - (int64_t)c * L;
+    for (int e = threadIdx.x; e < L * tc; e += blockDim.x) {
+        const int c = e / L;
+        const int l = e - c * L;
         double re = 0.0, im = 0.0;
         if (c < nc) {
             const int r = r0 + c;
@@ -334,16 +315,16 @@ __global__ __launch_bounds__(256) void unmix_kernel(FftPlan fp, const T *ypart, 
         b0[l * ldt + c] = {(T)re, (T)im};
     }
     __syncthreads();
-    cx<T> *res = fft_tile<T>(b0, b1, fp, ldt, tc, 1, (const cx<T> *)fp.tw);
+    cx<T> *res = fft_tile_rt<T, 1>(b0, b1, fp, ldt, tc, tw);
     const T scale = (T)(1.0 / sqrt((double)L));
-    for (int64_t e = threadIdx.x; e < L * tc; e += blockDim.x) {
-        const int64_t l = e / tc;
-        const int c = (int)(e - l * tc);
+    for (int e = threadIdx.x; e < L * tc; e += blockDim.x) {
+        const int l = e / tc;
+        const int c = e - l * tc;
         if (c >= nc) continue;
         const int r = r0 + c;
         const T v = (T)sign[l] * res[l * ldt + c].re * scale;
         if (rowmajor)
-            W[l * R + r] = v;
+            W[(int64_t)l * R + r] = v;
         else
             W[(int64_t)r * L + l] = v;
     }
@@ -377,13 +358,24 @@ FftPlan *fft_plan_get(int64_t L, bool dbl, hipError_t *err) {
     auto key = std::make_tuple(dev, L, dbl ? 1 : 0);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
+    // the generic tile (two buffers of L x 2 plus twiddles) must fit in LDS
+    if (L < 1 || L > (dbl ? 2048 : 4096)) {
+        *err = hipErrorInvalidValue;
+        return nullptr;
+    }
     FftPlan p{};
     p.L = L;
     int64_t rem = L;
-    while (rem % 4 == 0 && p.nrad < 24) { p.rad[p.nrad++] = 4; rem /= 4; }
+    while (rem % 4 == 0 && p.nrad < 24) {
+        p.rad[p.nrad++] = 4;
+        rem /= 4;
+    }
     const int primes[4] = {2, 3, 5, 7};
     for (int pi = 0; pi < 4; ++pi)
-        while (rem % primes[pi] == 0 && p.nrad < 24) { p.rad[p.nrad++] = primes[pi]; rem /= primes[pi]; }
+        while (rem % primes[pi] == 0 && p.nrad < 24) {
+            p.rad[p.nrad++] = primes[pi];
+            rem /= primes[pi];
+        }
     if (rem != 1) {
         *err = hipErrorInvalidValue;
         return nullptr;
@@ -412,71 +404,113 @@ FftPlan *fft_plan_get(int64_t L, bool dbl, hipError_t *err) {
     return heap;
 }
 
-static size_t tile_lds(int64_t L, int tc, size_t esz) { return 2 * (size_t)L * (tc + 1) * esz; }
-
-hipError_t launch_mix_pass(const FftPlan *fp, bool dbl, const ModeInfo &xi, const void *X, int xkind,
-                           void *Xhat, int32_t m, bool first, const int8_t *signs,
-                           double *normsq_part, int32_t *nparts, hipStream_t st) {
-    int64_t J = 1, K = 1;
-    for (int i = 0; i < m; ++i) J *= xi.dims[i];
-    for (int i = m + 1; i < xi.order; ++i) K *= xi.dims[i];
-    const size_t esz = dbl ? 16 : 8;
-    const int tc = tile_cols(fp->L, (int)esz);
-    const int64_t nb = ceil_div(J * K, tc);
-    if (nparts) *nparts = (int32_t)nb;
-    const size_t lds = tile_lds(fp->L, tc, esz);
-    if (dbl) {
-        hipLaunchKernelGGL((mix_pass_kernel<double, double>), dim3((unsigned)nb), dim3(256), lds, st, *fp,
-                           (const double *)X, (cx<double> *)Xhat, J, K, tc, first ? 1 : 0, xi, m, signs,
-                           normsq_part);
-    } else {
-        if (first && xkind == K_F64)
-            hipLaunchKernelGGL((mix_pass_kernel<float, double>), dim3((unsigned)nb), dim3(256), lds, st, *fp,
-                               (const double *)X, (cx<float> *)Xhat, J, K, tc, 1, xi, m, signs, normsq_part);
+template <int L, int TC, int NT>
+static hipError_t launch_ct_pass(const FftPlan *fp, const ModeInfo &xi, const void *X, int xkind, void *Xhat, int m,
+                                 bool first, const int8_t *signs, int64_t J, int64_t K, hipStream_t st) {
+    const unsigned nb = (unsigned)ceil_div(J * K, TC);
+    const cx<float> *tw = (const cx<float> *)fp->tw;
+    const bool xa = (((uintptr_t)X) & 15) == 0, ha = (((uintptr_t)Xhat) & 15) == 0;
+    if (first) {
+        if (xkind != K_F32) return hipErrorInvalidValue;
+        if (L % 4 == 0 && J == 1 && xa && ha)
+            hipLaunchKernelGGL((mix_pass_ct<float, L, TC, NT, true, (L % 4 == 0)>), dim3(nb), dim3(NT), 0, st,
+                               (const float *)X, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
         else
-            hipLaunchKernelGGL((mix_pass_kernel<float, float>), dim3((unsigned)nb), dim3(256), lds, st, *fp,
-                               (const float *)X, (cx<float> *)Xhat, J, K, tc, first ? 1 : 0, xi, m, signs,
-                               normsq_part);
+            hipLaunchKernelGGL((mix_pass_ct<float, L, TC, NT, true, false>), dim3(nb), dim3(NT), 0, st,
+                               (const float *)X, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
+    } else {
+        if (J > 1 && J % TC == 0 && ha)
+            hipLaunchKernelGGL((mix_pass_ct<float, L, TC, NT, false, true>), dim3(nb), dim3(NT), 0, st,
+                               (const float *)nullptr, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
+        else
+            hipLaunchKernelGGL((mix_pass_ct<float, L, TC, NT, false, false>), dim3(nb), dim3(NT), 0, st,
+                               (const float *)nullptr, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_factor_mix(const FftPlan *fp, bool dbl, int32_t I, int32_t R, const void *in,
-                             const int8_t *sign, void *out, bool inverse, hipStream_t st) {
+// Lengths with a compile-time schedule (single precision).
+static bool launch_fixed_length(int64_t L, const FftPlan *fp, const ModeInfo &xi, const void *X, int xkind,
+                                void *Xhat, int m, bool first, const int8_t *signs, int64_t J, int64_t K,
+                                hipStream_t st, hipError_t *err) {
+    switch (L) {
+        case 50: *err = launch_ct_pass<50, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
+        case 60: *err = launch_ct_pass<60, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
+        case 90: *err = launch_ct_pass<90, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
+        case 100: *err = launch_ct_pass<100, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
+        case 128: *err = launch_ct_pass<128, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
+        case 150: *err = launch_ct_pass<150, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
+        case 200: *err = launch_ct_pass<200, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
+        case 300: *err = launch_ct_pass<300, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
+        case 400: *err = launch_ct_pass<400, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
+        case 1000: *err = launch_ct_pass<1000, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
+        default: return false;
+    }
+}
+
+hipError_t launch_mix_pass(const FftPlan *fp, bool dbl, const ModeInfo &xi, const void *X, int xkind, void *Xhat,
+                           int32_t m, bool first, const int8_t *signs, double *normsq_part, int32_t *nparts,
+                           hipStream_t st) {
+    (void)normsq_part;
+    int64_t J = 1, K = 1;
+    for (int i = 0; i < m; ++i) J *= xi.dims[i];
+    for (int i = m + 1; i < xi.order; ++i) K *= xi.dims[i];
+    if (nparts) *nparts = 0;
+    if (!dbl && (!first || xkind == K_F32)) {
+        hipError_t e;
+        if (launch_fixed_length(fp->L, fp, xi, X, xkind, Xhat, m, first, signs, J, K, st, &e)) return e;
+    }
     const size_t esz = dbl ? 16 : 8;
-    const int tc = std::min(tile_cols(fp->L, (int)esz), (int)R);
-    const int nb = (int)ceil_div(R, tc);
+    const int tc = tile_cols(fp->L, (int)esz);
+    const int64_t nb = ceil_div(J * K, tc);
     const size_t lds = tile_lds(fp->L, tc, esz);
-    if (dbl)
-        hipLaunchKernelGGL(factor_mix_kernel<double>, dim3(nb), dim3(256), lds, st, *fp, (const double *)in,
-                           sign, (double *)out, R, tc, inverse ? 1 : 0);
-    else
-        hipLaunchKernelGGL(factor_mix_kernel<float>, dim3(nb), dim3(256), lds, st, *fp, (const float *)in,
-                           sign, (float *)out, R, tc, inverse ? 1 : 0);
+    if (dbl) {
+        hipLaunchKernelGGL((mix_pass_rt<double, double>), dim3((unsigned)nb), dim3(256), lds, st, *fp,
+                           (const double *)X, (cx<double> *)Xhat, J, K, tc, first ? 1 : 0, xi, m, signs);
+    } else if (first && xkind == K_F64) {
+        hipLaunchKernelGGL((mix_pass_rt<float, double>), dim3((unsigned)nb), dim3(256), lds, st, *fp,
+                           (const double *)X, (cx<float> *)Xhat, J, K, tc, 1, xi, m, signs);
+    } else {
+        hipLaunchKernelGGL((mix_pass_rt<float, float>), dim3((unsigned)nb), dim3(256), lds, st, *fp,
+                           (const float *)X, (cx<float> *)Xhat, J, K, tc, first ? 1 : 0, xi, m, signs);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_unmix(const FftPlan *fp, bool dbl, int32_t In, int32_t R, int32_t chunks,
-                        const void *ypart, const int8_t *sign, void *W, bool w_rowmajor,
-                        hipStream_t st) {
+hipError_t launch_factor_mix(const FftPlan *fp, bool dbl, int32_t I, int32_t R, const void *in, const int8_t *sign,
+                             void *out, bool inverse, hipStream_t st) {
     const size_t esz = dbl ? 16 : 8;
     const int tc = std::min(tile_cols(fp->L, (int)esz), (int)R);
     const int nb = (int)ceil_div(R, tc);
     const size_t lds = tile_lds(fp->L, tc, esz);
     if (dbl)
-        hipLaunchKernelGGL(unmix_kernel<double>, dim3(nb), dim3(256), lds, st, *fp, (const double *)ypart,
-                           chunks, R, sign, (double *)W, w_rowmajor ? 1 : 0, tc);
+        hipLaunchKernelGGL(factor_mix_kernel<double>, dim3(nb), dim3(256), lds, st, *fp, (const double *)in, sign,
+                           (double *)out, R, tc, inverse ? 1 : 0);
     else
-        hipLaunchKernelGGL(unmix_kernel<float>, dim3(nb), dim3(256), lds, st, *fp, (const float *)ypart,
-                           chunks, R, sign, (float *)W, w_rowmajor ? 1 : 0, tc);
+        hipLaunchKernelGGL(factor_mix_kernel<float>, dim3(nb), dim3(256), lds, st, *fp, (const float *)in, sign,
+                           (float *)out, R, tc, inverse ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_unmix(const FftPlan *fp, bool dbl, int32_t In, int32_t R, int32_t chunks, const void *ypart,
+                        const int8_t *sign, void *W, bool w_rowmajor, hipStream_t st) {
+    const size_t esz = dbl ? 16 : 8;
+    const int tc = std::min(tile_cols(fp->L, (int)esz), (int)R);
+    const int nb = (int)ceil_div(R, tc);
+    const size_t lds = tile_lds(fp->L, tc, esz);
+    if (dbl)
+        hipLaunchKernelGGL(unmix_kernel<double>, dim3(nb), dim3(256), lds, st, *fp, (const double *)ypart, chunks, R,
+                           sign, (double *)W, w_rowmajor ? 1 : 0, tc);
+    else
+        hipLaunchKernelGGL(unmix_kernel<float>, dim3(nb), dim3(256), lds, st, *fp, (const float *)ypart, chunks, R,
+                           sign, (float *)W, w_rowmajor ? 1 : 0, tc);
     return hipGetLastError();
 }
 
 hipError_t launch_signs(const ModeInfo &mi, uint64_t seed, int8_t *signs, hipStream_t st) {
     int64_t total = 0;
     for (int m = 0; m < mi.order; ++m) total += mi.dims[m];
-    hipLaunchKernelGGL(signs_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, mi, seed, signs,
-                       total);
+    hipLaunchKernelGGL(signs_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, mi, seed, signs, total);
     return hipGetLastError();
 }
 

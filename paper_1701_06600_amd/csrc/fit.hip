@@ -74,7 +74,29 @@ __global__ __launch_bounds__(kFitThreads) void fit_partial_kernel(FitArgs a) {
         e2 = dr * dr + di * di;
     }
     const double s = block_sum<kFitThreads>(e2, sh);
-    if (threadIdx.x == 0) a.part[blockIdx.x] = s;
+    if (threadIdx.x == 0) {
+        a.part[blockIdx.x] = s;
+        if (a.counter) {
+            // publish the partial, then let the last block finish (the
+            // device-scope fences order the partial stores of every block
+            // before the last block's reads, across L2 slices)
+            __threadfence();
+            const unsigned ticket = atomicAdd(a.counter, 1u);
+            if (ticket == gridDim.x - 1) {
+                __threadfence();
+                const volatile double *vp = a.part;
+                double tot = 0.0;
+                for (unsigned b = 0; b < gridDim.x; ++b) tot += vp[b];
+                const double f = 1.0 - sqrt(a.P * (tot / (double)a.P_hat)) / *a.normX;
+                const uint64_t t = a.t_dev ? *a.t_dev : 0;
+                if (a.fit_out) *a.fit_out = f;
+                if (a.hist) a.hist[t] = f;
+                if (a.hist_host) a.hist_host[t] = f;
+                if (a.t_dev) *a.t_dev = t + 1;
+                *a.counter = 0u;
+            }
+        }
+    }
 }
 
 hipError_t launch_fit_partial(const FitArgs &a, int32_t *nblocks, hipStream_t st) {

@@ -35,7 +35,9 @@ struct GatherPlan {
 
 // Choose tiling for one mode step.  elem_align: true when the data pointer
 // and every stride other than mode n allow 16-byte vector loads along fibers.
-GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_ok);
+// max_chunks > 0 caps the number of sample chunks (partial products) for
+// consumers that sum them inside one workgroup.
+GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks = 0);
 
 struct GatherArgs {
     ModeInfo mi;
@@ -101,6 +103,28 @@ struct SolveArgs {
     int32_t info_sticky;   // 1: only ever set the flag; 0: also clear it on success
 };
 hipError_t launch_solve(const SolveArgs &a, int32_t *nblocks, hipStream_t st);
+
+// The whole post-gather part of a mode step in one workgroup (step.hip).
+struct StepArgs {
+    int32_t In, R;
+    const double *vpart;
+    int32_t vparts;
+    const void *W;          // real: (p, i, r) at W[p*wps + i*wsi + r*wsr]; MIX: [wparts][2R][In]
+    int32_t wparts;
+    int64_t wps, wsi, wsr;
+    bool wdouble;
+    bool mix;
+    const int8_t *sign;     // D_n (MIX)
+    const float *Wref;      // refinement partials or NULL
+    int32_t wrefparts;
+    int64_t rps, rsi, rsr;
+    void *A;                // row-major In x R, real type
+    void *Ahat;             // MIX: row-major In x R complex
+    double *lambda;
+    int32_t *info;          // set to CPRAND_W_PINV when the pseudo-inverse was used
+};
+size_t step_finish_lds(int32_t In, int32_t R, bool mix, bool dbl);
+hipError_t launch_step_finish(const StepArgs &a, const FftPlan *fp, bool dbl, hipStream_t st);
 hipError_t launch_normalize(int32_t In, int32_t R, void *A, bool adouble,
                             const double *colsq_part, int32_t nblocks, double *lambda,
                             hipStream_t st);
@@ -118,6 +142,16 @@ struct FitArgs {
     int32_t P_hat;
     uint64_t seed;
     double *part;         // per-block partial sums
+    // Optional single-launch finish: the last block to finish sums the
+    // partials, writes F-hat to fit_out / hist[t] / hist_host[t], advances
+    // *t_dev and clears *counter (which must start at zero).
+    unsigned *counter;
+    double P;
+    const double *normX;
+    double *fit_out;
+    double *hist;
+    double *hist_host;
+    uint64_t *t_dev;
 };
 hipError_t launch_fit_partial(const FitArgs &a, int32_t *nblocks, hipStream_t st);
 // fit_out = 1 - sqrt(P * sum(part)/P_hat) / *normX; also hist[t] (t from t_dev) if hist.
@@ -127,6 +161,27 @@ hipError_t launch_fit_final(const double *part, int32_t nparts, int32_t P_hat, d
 hipError_t launch_normsq_partial(const ModeInfo &mi, const void *X, int kind, double *part,
                                  int32_t *nparts, hipStream_t st);
 hipError_t launch_sqrt_sum(const double *part, int32_t nparts, double *out, hipStream_t st);
+
+// ---- proposals and the proposal network (proposal.hip) ------------------------------
+constexpr int kMlpParams = 4545;
+// per-mode stats (doubles): G [R*R], G^{-1} [R*R], |A|_F^2, mean |cosine|
+inline size_t mode_stats_doubles(int R) { return 2 * (size_t)R * R + 2; }
+hipError_t launch_mode_stats(const FactorPtrs &A, const ModeInfo &mi, int32_t R, double *stats, int32_t skip,
+                             hipStream_t st);
+hipError_t launch_marginal_h(const ModeInfo &mi, int32_t R, const double *stats, double *H, hipStream_t st);
+hipError_t launch_row_scores(const FactorPtrs &A, const ModeInfo &mi, int32_t R, const double *stats, const double *H,
+                             const float *params, bool learned, float *const *score, float *feat, float *target,
+                             const int64_t *row_off, hipStream_t st);
+// alpha_dev (device) overrides alpha when non-NULL
+hipError_t launch_cdf(const ModeInfo &mi, float *const *score, double alpha, const double *alpha_dev,
+                      uint64_t *const *cdf, hipStream_t st);
+hipError_t launch_mlp_logits(const float *params, const float *X, int64_t rows, float *z, hipStream_t st);
+hipError_t launch_group_ce(const float *z, const float *t, const int64_t *goff, int32_t ngroups, float *dz,
+                           double *gloss, hipStream_t st);
+int32_t mlp_grad_blocks(int64_t rows);
+hipError_t launch_mlp_grad(const float *params, const float *X, const float *dz, int64_t rows, float *gpart,
+                           float *grad, hipStream_t st);
+hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int32_t step, float lr, hipStream_t st);
 
 // ---- layout --------------------------------------------------------------------------
 hipError_t launch_layout_copy(const ModeInfo &xi, const void *X, int xkind, int32_t n,

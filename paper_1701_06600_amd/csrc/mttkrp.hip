@@ -277,10 +277,10 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-GatherPlan plan_gather_bf16(int32_t R, int32_t S, int64_t In, bool contig_ok);
+GatherPlan plan_gather_bf16(int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks);
 
-GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_ok) {
-    if (kind == K_BF16) return plan_gather_bf16(R, S, In, contig_ok);
+GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks) {
+    if (kind == K_BF16) return plan_gather_bf16(R, S, In, contig_ok, max_chunks);
     GatherPlan g{};
     g.kind = kind;
     g.R = R;
@@ -304,8 +304,13 @@ GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_o
         return head + (size_t)k * ldb * tsize * 2;  // room for Bre + (Bim or Zraw)
     };
     int kc = 64;
-    while (kc < 512 && (int64_t)g.row_blocks * ceil_div(S, 2 * kc) >= 2048 && lds_for(2 * kc) <= 65536) kc *= 2;
-    while (kc > 16 && ((int64_t)g.row_blocks * ceil_div(S, kc) < 256 || lds_for(kc) > 65536)) kc /= 2;
+    if (max_chunks > 0) {
+        kc = (int)ceil_div(ceil_div(S, max_chunks), 16) * 16;
+        while (kc > 16 && lds_for(kc) > 150 * 1024) kc -= 16;
+    } else {
+        while (kc < 512 && (int64_t)g.row_blocks * ceil_div(S, 2 * kc) >= 2048 && lds_for(2 * kc) <= 65536) kc *= 2;
+        while (kc > 16 && ((int64_t)g.row_blocks * ceil_div(S, kc) < 256 || lds_for(kc) > 65536)) kc /= 2;
+    }
     g.kc = kc;
     g.chunks = (int)ceil_div(S, kc);
     g.contig = contig_ok;

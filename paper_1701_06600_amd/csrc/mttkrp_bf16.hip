@@ -199,7 +199,7 @@ hipError_t launch_bf16_gather(const GatherPlan &gp, const GatherArgs &g, hipStre
     return hipGetLastError();
 }
 
-GatherPlan plan_gather_bf16(int32_t R, int32_t S, int64_t In, bool contig_ok) {
+GatherPlan plan_gather_bf16(int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks) {
     GatherPlan g{};
     g.kind = K_BF16;
     g.R = R;
@@ -211,13 +211,20 @@ GatherPlan plan_gather_bf16(int32_t R, int32_t S, int64_t In, bool contig_ok) {
     g.rows_wg = kBfRows;
     g.row_blocks = (int)ceil_div(In, kBfRows);
     int kc = 128;
-    while (kc > kBfStep && (int64_t)g.row_blocks * ceil_div(S, kc) < 256) kc /= 2;
+    if (max_chunks > 0)
+        kc = (int)std::min<int64_t>(512, ceil_div(ceil_div(S, max_chunks), kBfStep) * kBfStep);
+    else
+        while (kc > kBfStep && (int64_t)g.row_blocks * ceil_div(S, kc) < 256) kc /= 2;
+    auto lds_for = [&](int k) {
+        const size_t head = (((size_t)k * (16 + 4 * kMaxOrder)) + 15) & ~(size_t)15;
+        return head + (size_t)k * R * 4 + (size_t)16 * g.ct * (k + 8) * 2 + (size_t)kBfRows * (kBfStep + kBfPadA) * 2 +
+               16;
+    };
+    while (kc > kBfStep && lds_for(kc) > 150 * 1024) kc -= kBfStep;
     g.kc = kc;
     g.chunks = (int)ceil_div(S, kc);
     g.contig = contig_ok;
-    const size_t head = (((size_t)kc * (16 + 4 * kMaxOrder)) + 15) & ~(size_t)15;
-    g.lds_bytes = head + (size_t)kc * R * 4 + (size_t)16 * g.ct * (kc + 8) * 2 +
-                  (size_t)kBfRows * (kBfStep + kBfPadA) * 2 + 16;
+    g.lds_bytes = lds_for(kc);
     return g;
 }
 

@@ -129,6 +129,25 @@ def make_problem(dims, R, congruence=None, noise=0.01, seed=SEED_BASE,
     return Problem(tuple(dims), R, lam, factors, init, noise, seed, spikes)
 
 
+def mlp_init(seed=SEED_BASE, n_in=4, h1=64, h2=64):
+    """Initial parameters of the 4-64-64-1 proposal network (uniform in
+    +-1/sqrt(fan-in), zero biases), flat in the library's layout:
+    W1 (h1 x n_in), b1, W2 (h2 x h1), b2, w3 (h2), b3."""
+    rng = _rng(seed, 8)
+    W1 = rng.uniform(-1, 1, (h1, n_in)) / math.sqrt(n_in)
+    W2 = rng.uniform(-1, 1, (h2, h1)) / math.sqrt(h1)
+    w3 = rng.uniform(-1, 1, h2) / math.sqrt(h2)
+    return np.concatenate([W1.ravel(), np.zeros(h1), W2.ravel(), np.zeros(h2), w3, np.zeros(1)])
+
+
+def training_problems(n_inst, dims, R, congruence, spiky, noise=0.01, seed=SEED_BASE + 9):
+    """Problems for training the proposal network: instance k draws its
+    factors, tensor and initial factors like make_problem with seed
+    seed + 1000 k.  The training targets come from the true factors, the
+    initial factors and ALS iterates computed from them by the caller."""
+    return [make_problem(dims, R, congruence, noise, seed + 1000 * k, spiky) for k in range(n_inst)]
+
+
 def problem_for(workload: Workload, R_model=None):
     w = workload
     return make_problem(w.dims, w.R, w.congruence, w.noise, w.seed, w.spiky,

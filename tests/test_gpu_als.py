@@ -95,6 +95,23 @@ def test_cprand_bf16_refined_reaches_fp64_fit():
     assert abs(F2 - OC.exact_fit(X, lam_r, A_r)) < 1e-3
 
 
+@pytest.mark.parametrize("mix", [0, 1])
+def test_multi_kernel_step_path_tracks_oracle(mix):
+    """A 1000-row mode is too large for the one-workgroup step and takes the
+    multi-kernel solve path; the other modes take the fused path."""
+    p = synth.make_problem((1000, 12, 10), 10, congruence=0.5, noise=0.01, seed=12)
+    X = synth.dense_tensor(p)
+    R, S, it = 10, 300, 6
+    out, A = _run_gpu(X, p.init, R, S, 77, torch.float64, max_iters=it, mix=mix)
+    if mix:
+        lam_r, A_r, hist_r = OC.cprand_mix(X, R, S, p.init, 77, it)
+    else:
+        lam_r, A_r, hist_r = OC.cprand(X, R, S, p.init, 77, it)
+    assert np.max(np.abs(np.array(out["fit_history"]) - np.array(hist_r))) < 1e-8
+    for a, b in zip(A, A_r):
+        assert np.allclose(a, b, atol=1e-7)
+
+
 def test_cprand_fixed_proposal_tracks_oracle():
     p = synth.make_problem((30, 40, 50), 4, congruence=0.5, noise=0.01, seed=10, spiky=0.1)
     X = synth.dense_tensor(p)
