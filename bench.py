@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--layout", type=int, default=1, help="0: mode-major copies of X-hat, 1: strided gathers")
     ap.add_argument("--legs", default="main,precision,learned")
     ap.add_argument("--train-instances", type=int, default=200)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
     legs = set(args.legs.split(","))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -58,6 +60,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        n = (1 << 30) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
+        return
 
     import paper_1701_06600_amd as P
     import synth
