@@ -286,14 +286,15 @@ def learned_leg(P, synth, torch, dev, n_inst):
     X = synth.device_tensor(prob, dev, "f32")
     Xv = P.View(X, w.dims)
     init = [torch.as_tensor(M, dtype=torch.float32, device=dev) for M in prob.init]
-    res = {"workload": "1000x1000x1000 FP32, R=50, congruence 0.9, 10% rows x20, 1% noise, S=2000, "
-                       "paper stop rule (200 iterations, |dF| <= 1e-4, F >= 0.988)",
+    res = {"workload": "1000x1000x1000 FP32, R=50, congruence 0.9, 10% rows x20, 1% noise, S=2000; each "
+                       "method runs until F-hat >= 1 - 1.2 eta = 0.988 (the paper's fit target) or 200 "
+                       "iterations (no |dF| rule, so all methods are compared at the same fit)",
            "training": {"instances": n_inst, "rows": rows, "epochs": epochs, "loss_first": hist[0],
                         "loss_last": hist[-1], "build_s": t_build, "train_s": t_train}}
     runs = (("uniform", P.PROPOSAL_UNIFORM, P.MIX_NONE), ("mix", P.PROPOSAL_UNIFORM, P.MIX_FFT),
             ("learned", P.PROPOSAL_LEARNED, P.MIX_NONE), ("marginal", P.PROPOSAL_MARGINAL, P.MIX_NONE))
     for name, prop, mix in runs:
-        opts = P.make_opts(R, S, P_hat=w.P_hat, max_iters=w.max_iters, seed=w.seed, tol=w.tol,
+        opts = P.make_opts(R, S, P_hat=w.P_hat, max_iters=w.max_iters, seed=w.seed, tol=0.0,
                            fit_target=w.fit_target, mix=mix, proposal=prop, alpha=0.1, layout=1, use_graph=1,
                            mlp_params=theta if prop == P.PROPOSAL_LEARNED else None)
         plan = P.Plan(Xv, opts)
@@ -301,7 +302,8 @@ def learned_leg(P, synth, torch, dev, n_inst):
         plan.close()
         fit = _exact_fit(torch, X, w.dims, r["lambda"], r["A"])
         res[name] = {"iters": r["iters"], "s_per_decomposition": sec, "iters_per_s": r["iters"] / sec,
-                     "final_fit_est": r["fit_est"], "exact_fit": fit, "fell_back": bool(r["flags"] & P.W_FALLBACK)}
+                     "final_fit_est": r["fit_est"], "exact_fit": fit, "reached_target": r["fit_est"] >= w.fit_target,
+                     "fell_back": bool(r["flags"] & P.W_FALLBACK)}
         print("[bench] %s: %d iters, %.3f s, F-hat %.5f, fit %.5f" % (name, r["iters"], sec, r["fit_est"], fit),
               flush=True)
     return res

@@ -75,7 +75,10 @@ struct cprand_plan {
     double *normX = nullptr;
     double *hist_dev = nullptr;
     double *hist_host = nullptr;
-    void *wtmp = nullptr;
+    void *wtmp = nullptr;   // maxdim x R doubles: summed (or unmixed) MTTKRP of the split path
+    double *vsum = nullptr; // R x R: summed Gram of the split path
+    int32_t *frow = nullptr; // the fixed fit set: rows [P_hat][N] and tensor values [P_hat][2]
+    double *fx = nullptr;
     void *ysum = nullptr;
     uint64_t *t_dev = nullptr;
     unsigned *counter = nullptr;
@@ -84,7 +87,7 @@ struct cprand_plan {
     int64_t *seg_off = nullptr;
     // importance proposals recomputed every mode step (LEARNED / MARGINAL)
     bool adaptive = false;
-    double *pstats = nullptr, *pH = nullptr, *alpha_dev = nullptr;
+    double *pstats = nullptr, *pH = nullptr, *pgpart = nullptr, *alpha_dev = nullptr;
     float *pscore[CPRAND_MAX_ORDER] = {};
     uint64_t *pcdf[CPRAND_MAX_ORDER] = {};
     // saved (factors, lambda) states for the proposal fallback: the iterate
@@ -147,9 +150,54 @@ struct Stop {
     }
 };
 
+// Sample chunks of the in-loop gathers: the fused step sums at most
+// kChunksFused partial products inside its workgroup; the split path sums
+// up to kChunksSplit with separate coalesced kernels.
+constexpr int kChunksFused = 8, kChunksSplit = 32;
+
 const void *view_ptr(const cprand_plan *p, const View &v, const void *xdata) {
     if (v.data) return v.data;
     return v.from_xhat ? p->xhat : xdata;
+}
+
+// The sampled fit estimate of the current model: against X-hat and the mixed
+// factors under mixing, else against X (Section 3.4).
+FitArgs fit_args(const cprand_plan *p, const void *xdata) {
+    const int N = p->N;
+    FitArgs fa{};
+    fa.mi.order = N;
+    for (int m = 0; m < N; ++m) {
+        fa.mi.dims[m] = p->dims[m];
+        fa.mi.strides[m] = p->xstrides[m];
+        fa.A.p[m] = p->mix ? p->fhat[m] : p->fac[m];
+    }
+    if (p->mix) {
+        int64_t s = 1;
+        for (int m = 0; m < N; ++m) {
+            fa.mi.strides[m] = s;
+            s *= p->dims[m];
+        }
+        fa.X = p->xhat;
+        fa.kind = p->dbl ? K_C128 : K_C64;
+        fa.cplx = true;
+    } else {
+        fa.X = xdata;
+        fa.kind = p->xkind;
+        fa.cplx = false;
+    }
+    fa.fdouble = p->dbl;
+    fa.lambda = p->lambda;
+    fa.R = p->o.R;
+    fa.P_hat = p->o.P_hat;
+    fa.seed = p->o.seed;
+    fa.part = p->fitpart;
+    fa.counter = p->counter;
+    fa.P = (double)p->P;
+    fa.normX = p->normX;
+    fa.hist = p->hist_dev;
+    fa.hist_host = p->hist_mapped;
+    fa.t_dev = p->t_dev;
+    return fa;
 }
 
 // One outer iteration on `st`.
@@ -161,9 +209,18 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         const void *vd = view_ptr(p, v, xdata);
         const int64_t In = p->dims[n];
         // the whole post-gather step in one workgroup when it fits in LDS
-        const bool fused = step_finish_lds((int32_t)In, R, p->mix, p->dbl) <= 156 * 1024;
-        const int maxc = fused ? 8 : 0;
-        GatherPlan gp = plan_gather(p->gkind, R, p->o.S, In, v.data ? true : contig_x[n], maxc);
+        bool fused = step_finish_lds((int32_t)In, R, p->mix, p->dbl) <= 156 * 1024;
+        const bool rcontig = p->refine && (p->rview[n].data ? true : contig_x[n]);
+        GatherPlan gp = plan_gather(p->gkind, R, p->o.S, In, v.data ? true : contig_x[n],
+                                    fused ? kChunksFused : kChunksSplit);
+        GatherPlan gr = p->refine ? plan_gather(K_F32, R, p->o.S, In, rcontig, fused ? kChunksFused : kChunksSplit)
+                                  : GatherPlan{};
+        if (fused && (gp.chunks > kChunksFused || (p->refine && gr.chunks > kChunksFused))) {
+            // the LDS limit shrank the chunks: too many partials for the fused step
+            fused = false;
+            gp = plan_gather(p->gkind, R, p->o.S, In, v.data ? true : contig_x[n], kChunksSplit);
+            if (p->refine) gr = plan_gather(K_F32, R, p->o.S, In, rcontig, kChunksSplit);
+        }
         GatherArgs ga{};
         ga.mi.order = N;
         ga.mi.n = n;
@@ -189,8 +246,7 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
                 pm.strides[m] = 1;
                 fp.p[m] = (m == n) ? nullptr : p->fac[m];
             }
-            e = launch_mode_stats(fp, pm, R, p->pstats, n, st);
-            if (e == hipSuccess && !learned) e = launch_marginal_h(pm, R, p->pstats, p->pH, st);
+            e = launch_mode_stats(fp, pm, R, p->pstats, p->pgpart, learned ? nullptr : p->pH, st);
             if (e == hipSuccess)
                 e = launch_row_scores(fp, pm, R, p->pstats, learned ? nullptr : p->pH, p->o.mlp_params, learned,
                                       p->pscore, nullptr, nullptr, nullptr, st);
@@ -206,10 +262,8 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         ga.wpart = p->wpart;
         ga.vpart = p->vpart;
         e = launch_gather(gp, ga, st);
-        GatherPlan gr{};
         if (e == hipSuccess && p->refine) {
             const View &rv = p->rview[n];
-            gr = plan_gather(K_F32, R, p->o.S, In, rv.data ? true : contig_x[n], maxc);
             GatherArgs g2 = ga;
             for (int m = 0; m < N; ++m) g2.mi.strides[m] = rv.strides[m];
             g2.X = view_ptr(p, rv, xdata);
@@ -248,12 +302,18 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
             if (e == hipSuccess) e = launch_step_finish(sa, fp, p->dbl, st);
             continue;
         }
+        // the split path: partial products summed by coalesced FP64 kernels first
         SolveArgs sa{};
         sa.In = (int32_t)In;
         sa.R = R;
         sa.vpart = p->vpart;
         sa.vparts = gp.chunks;
-        if (p->mix) {
+        if (gp.chunks > 1) {
+            e = launch_sum_parts_f64(p->vpart, gp.chunks, (int64_t)R * R, true, p->vsum, st);
+            sa.vpart = p->vsum;
+            sa.vparts = 1;
+        }
+        if (e == hipSuccess && p->mix) {
             const void *y = p->wpart;
             int32_t np = gp.chunks;
             if (np > 8) {
@@ -268,14 +328,16 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
             sa.W = p->wtmp;
             sa.wparts = 1;
             sa.wps = 0;
-        } else {
-            sa.W = p->wpart;
-            sa.wparts = gp.chunks;
-            sa.wps = (int64_t)R * In;
+            sa.wdouble = p->dbl;
+        } else if (e == hipSuccess) {
+            e = launch_sum_parts_f64(p->wpart, gp.chunks, (int64_t)R * In, p->dbl, (double *)p->wtmp, st);
+            sa.W = p->wtmp;
+            sa.wparts = 1;
+            sa.wps = 0;
+            sa.wdouble = true;
         }
         sa.wsi = 1;
         sa.wsr = In;
-        sa.wdouble = p->dbl;
         if (p->refine) {
             sa.Wref = (const float *)p->rpart;
             sa.wrefparts = gr.chunks;
@@ -298,39 +360,9 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         }
     }
     if (e != hipSuccess) return e;
-    FitArgs fa{};
-    fa.mi.order = N;
-    for (int m = 0; m < N; ++m) {
-        fa.mi.dims[m] = p->dims[m];
-        fa.mi.strides[m] = p->xstrides[m];
-        fa.A.p[m] = p->mix ? p->fhat[m] : p->fac[m];
-    }
-    if (p->mix) {
-        int64_t s = 1;
-        for (int m = 0; m < N; ++m) {
-            fa.mi.strides[m] = s;
-            s *= p->dims[m];
-        }
-        fa.X = p->xhat;
-        fa.kind = p->dbl ? K_C128 : K_C64;
-        fa.cplx = true;
-    } else {
-        fa.X = xdata;
-        fa.kind = p->xkind;
-        fa.cplx = false;
-    }
-    fa.fdouble = p->dbl;
-    fa.lambda = p->lambda;
-    fa.R = R;
-    fa.P_hat = p->o.P_hat;
-    fa.seed = p->o.seed;
-    fa.part = p->fitpart;
-    fa.counter = p->counter;
-    fa.P = (double)p->P;
-    fa.normX = p->normX;
-    fa.hist = p->hist_dev;
-    fa.hist_host = p->hist_mapped;
-    fa.t_dev = p->t_dev;
+    FitArgs fa = fit_args(p, xdata);
+    fa.frow = p->frow;
+    fa.fx = p->fx;
     int32_t nb = 0;
     return launch_fit_partial(fa, &nb, st);
 }
@@ -467,7 +499,7 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     size_t wpart = 0, vpart = 0, rpart = 0;
     int64_t maxdim = 1;
     for (int n = 0; n < N; ++n) {
-        for (int maxc : {0, 8}) {  // the per-step path and the fused path
+        for (int maxc : {kChunksSplit, kChunksFused}) {  // the split path and the fused path
             GatherPlan gp = plan_gather(p->gkind, R, o.S, p->dims[n], true, maxc);
             const size_t gts = (p->gkind == K_F64 || p->gkind == K_C128) ? 8 : 4;
             wpart = std::max(wpart, gp.wpart_elems() * gts);
@@ -494,12 +526,16 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     if (e == hipSuccess) e = dalloc(p, (void **)&p->normpart, 4096 * 8);
     if (e == hipSuccess) e = dalloc(p, (void **)&p->normX, 8);
     if (e == hipSuccess) e = dalloc(p, (void **)&p->hist_dev, (size_t)o.max_iters * 8);
-    if (e == hipSuccess) e = dalloc(p, &p->wtmp, (size_t)maxdim * R * tsz);
+    if (e == hipSuccess) e = dalloc(p, &p->wtmp, (size_t)maxdim * R * 8);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->vsum, (size_t)R * R * 8);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->frow, (size_t)o.P_hat * N * 4);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->fx, (size_t)o.P_hat * 16);
     if (e == hipSuccess && p->mix) e = dalloc(p, &p->ysum, (size_t)maxdim * 2 * R * tsz);
     p->adaptive = o.proposal == CPRAND_PROPOSAL_LEARNED || o.proposal == CPRAND_PROPOSAL_MARGINAL;
     if (e == hipSuccess && p->adaptive) {
         e = dalloc(p, (void **)&p->pstats, (size_t)N * mode_stats_doubles(R) * 8);
-        if (e == hipSuccess) e = dalloc(p, (void **)&p->pH, (size_t)N * R * R * 8);
+        if (e == hipSuccess) e = dalloc(p, (void **)&p->pH, (size_t)R * R * 8);
+        if (e == hipSuccess) e = dalloc(p, (void **)&p->pgpart, gram_part_doubles(N, R) * 8);
         for (int m = 0; m < N && e == hipSuccess; ++m) {
             e = dalloc(p, (void **)&p->pscore[m], (size_t)p->dims[m] * 4);
             if (e == hipSuccess) e = dalloc(p, (void **)&p->pcdf[m], (size_t)(p->dims[m] + 1) * 8);
@@ -625,6 +661,8 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
             timed_lay[n] = any && e == hipSuccess;
         }
     }
+    // the fixed fit set: rows and tensor values drawn once per run
+    if (e == hipSuccess) e = launch_fit_set(fit_args(p, X->data), p->frow, p->fx, st);
     if (e == hipSuccess) e = hipEventRecord(p->ev[1], st);
     if (e != hipSuccess) return hip_fail(e, "setup");
 

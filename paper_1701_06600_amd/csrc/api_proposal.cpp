@@ -12,14 +12,15 @@ namespace cprand {
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct PropWs {
-    size_t stats, H, score, total;
+    size_t stats, H, gpart, score, total;
 };
 
 static PropWs prop_layout(int32_t order, const int64_t *dims, int32_t R) {
     PropWs w{};
     w.stats = 0;
     w.H = align256(w.stats + (size_t)order * mode_stats_doubles(R) * 8);
-    w.score = align256(w.H + (size_t)order * R * R * 8);
+    w.gpart = align256(w.H + (size_t)R * R * 8);
+    w.score = align256(w.gpart + gram_part_doubles(order, R) * 8);
     size_t rows = 0;
     for (int m = 0; m < order; ++m) rows += (size_t)align256((size_t)dims[m] * 4);
     w.total = align256(w.score + rows);
@@ -53,8 +54,8 @@ static hipError_t prop_common(int32_t order, const int64_t *dims, int32_t n, int
     }
     double *stats = (double *)((char *)ws + L.stats);
     double *H = (double *)((char *)ws + L.H);
-    hipError_t e = launch_mode_stats(fp, mi, R, stats, n, st);
-    if (e == hipSuccess && need_h) e = launch_marginal_h(mi, R, stats, H, st);
+    double *gpart = (double *)((char *)ws + L.gpart);
+    hipError_t e = launch_mode_stats(fp, mi, R, stats, gpart, need_h ? H : nullptr, st);
     if (e == hipSuccess)
         e = launch_row_scores(fp, mi, R, stats, need_h ? H : nullptr, params, learned, score, feat, target, row_off,
                               st);

@@ -101,27 +101,59 @@ __device__ inline void small_dft(cx<T> *v, const cx<T> *tw, int L) {
 
 // ---------------------------------------------------------------------------
 // Generic path: radices known at run time, ping-pong between two tiles.
+// a = q b + r for 0 <= a < 2^22 and 1 <= b < 2^11: a float estimate of the
+// quotient (off by at most one) and one correction; binv = 1.0f / b.
+__device__ inline int divmod_small(int a, int b, float binv, int &r) {
+    int q = (int)((float)a * binv);
+    r = a - q * b;
+    if (r < 0) {
+        --q;
+        r += b;
+    } else if (r >= b) {
+        ++q;
+        r -= b;
+    }
+    return q;
+}
+
 template <typename T, int R, int DIR>
 __device__ inline void stage_rt(const cx<T> *in, cx<T> *out, int L, int ldt, int tc, int Ns, const cx<T> *tw) {
     const int nb = (L / R) * tc;
     const int twstep = L / (Ns * R);
-    for (int id = threadIdx.x; id < nb; id += blockDim.x) {
-        const int col = id % tc;
-        const int j = id / tc;
-        const int k = j % Ns;
-        cx<T> v[R];
+    const int LR = L / R;
+    const float tcinv = 1.0f / (float)tc, nsinv = 1.0f / (float)Ns;
+    const int nt = blockDim.x;
+    // two butterflies per pass so that both sets of LDS loads are in flight
+    for (int id0 = threadIdx.x; id0 < nb; id0 += 2 * nt) {
+        cx<T> v[2][R];
+        int col[2], j[2], k[2];
+        bool on[2];
 #pragma unroll
-        for (int t = 0; t < R; ++t) v[t] = in[(j + t * (L / R)) * ldt + col];
+        for (int h = 0; h < 2; ++h) {
+            const int id = id0 + h * nt;
+            on[h] = id < nb;
+            j[h] = divmod_small(on[h] ? id : 0, tc, tcinv, col[h]);
+            int kk;
+            (void)divmod_small(j[h], Ns, nsinv, kk);
+            k[h] = kk;
 #pragma unroll
-        for (int t = 1; t < R; ++t) {
-            cx<T> w = tw[t * k * twstep];
-            if (DIR > 0) w.im = -w.im;
-            v[t] = cmul(v[t], w);
+            for (int t = 0; t < R; ++t) v[h][t] = on[h] ? in[(j[h] + t * LR) * ldt + col[h]] : cx<T>{};
         }
-        small_dft<T, R, DIR>(v, tw, L);
-        const int o = (j / Ns) * Ns * R + k;
 #pragma unroll
-        for (int t = 0; t < R; ++t) out[(o + t * Ns) * ldt + col] = v[t];
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                cx<T> w = tw[t * k[h] * twstep];
+                if (DIR > 0) w.im = -w.im;
+                v[h][t] = cmul(v[h][t], w);
+            }
+            small_dft<T, R, DIR>(v[h], tw, L);
+            if (on[h]) {
+                const int o = (j[h] - k[h]) * R + k[h];
+#pragma unroll
+                for (int t = 0; t < R; ++t) out[(o + t * Ns) * ldt + col[h]] = v[h][t];
+            }
+        }
     }
 }
 

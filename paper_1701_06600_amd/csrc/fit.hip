@@ -30,45 +30,106 @@ __device__ inline void load_elem(const void *X, int kind, int64_t o, double &re,
     }
 }
 
+// Multi-index and tensor value of fit sample p (Philox counter (p, 0, 0, block)).
+__device__ inline void fit_entry(const FitArgs &a, int64_t p, int64_t *row, double &xr, double &xi) {
+    const int N = a.mi.order;
+    u64x4 blk;
+    int64_t off = 0;
+    for (int k = 0; k < N; ++k) {
+        if ((k & 3) == 0) blk = philox4x64_10((uint64_t)p, 0, 0, (uint64_t)(k >> 2), a.seed, kTagFit);
+        row[k] = (int64_t)mulhi64(blk.v[k & 3], (uint64_t)a.mi.dims[k]);
+        off += row[k] * a.mi.strides[k];
+    }
+    load_elem(a.X, a.kind, off, xr, xi);
+}
+
+__global__ __launch_bounds__(kFitThreads) void fit_set_kernel(FitArgs a, int32_t *frow, double *fx) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P_hat) return;
+    int64_t row[kMaxOrder];
+    double xr, xi;
+    fit_entry(a, p, row, xr, xi);
+    for (int k = 0; k < a.mi.order; ++k) frow[p * a.mi.order + k] = (int32_t)row[k];
+    fx[2 * p] = xr;
+    fx[2 * p + 1] = xi;
+}
+
+hipError_t launch_fit_set(const FitArgs &a, int32_t *frow, double *fx, hipStream_t st) {
+    hipLaunchKernelGGL(fit_set_kernel, dim3((unsigned)ceil_div(a.P_hat, kFitThreads)), dim3(kFitThreads), 0, st, a,
+                       frow, fx);
+    return hipGetLastError();
+}
+
+// Factor entry (r) of row `row` of mode m, real and imaginary parts.
+__device__ inline void factor_entry(const FitArgs &a, int m, int64_t row, int r, double &ar, double &ai) {
+    const int64_t o = row * a.R + r;
+    if (!a.cplx) {
+        ar = a.fdouble ? ((const double *)a.A.p[m])[o] : (double)((const float *)a.A.p[m])[o];
+        ai = 0.0;
+    } else if (a.fdouble) {
+        ar = ((const double *)a.A.p[m])[2 * o];
+        ai = ((const double *)a.A.p[m])[2 * o + 1];
+    } else {
+        ar = (double)((const float *)a.A.p[m])[2 * o];
+        ai = (double)((const float *)a.A.p[m])[2 * o + 1];
+    }
+}
+
 __global__ __launch_bounds__(kFitThreads) void fit_partial_kernel(FitArgs a) {
     __shared__ double sh[kFitThreads / kWave];
+    __shared__ int s_last;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double e2 = 0.0;
     if (p < a.P_hat) {
         const int N = a.mi.order;
         int64_t row[kMaxOrder];
-        u64x4 blk;
-        int64_t off = 0;
-        for (int k = 0; k < N; ++k) {
-            if ((k & 3) == 0) blk = philox4x64_10((uint64_t)p, 0, 0, (uint64_t)(k >> 2), a.seed, kTagFit);
-            row[k] = (int64_t)mulhi64(blk.v[k & 3], (uint64_t)a.mi.dims[k]);
-            off += row[k] * a.mi.strides[k];
-        }
         double xr, xi;
-        load_elem(a.X, a.kind, off, xr, xi);
+        if (a.frow) {
+            for (int k = 0; k < N; ++k) row[k] = a.frow[p * N + k];
+            xr = a.fx[2 * p];
+            xi = a.fx[2 * p + 1];
+        } else {
+            fit_entry(a, p, row, xr, xi);
+        }
+        // model entry sum_r lambda_r prod_m A^(m)(i_m, r), four ranks at a time
+        // so that their factor loads are in flight together (same order of
+        // operations as one rank at a time)
         double mr = 0.0, mi = 0.0;
-        for (int r = 0; r < a.R; ++r) {
-            double zr = a.lambda[r], zi = 0.0;
-            for (int m = 0; m < N; ++m) {
-                const int64_t o = row[m] * a.R + r;
-                if (!a.cplx) {
-                    zr *= a.fdouble ? ((const double *)a.A.p[m])[o] : (double)((const float *)a.A.p[m])[o];
-                } else {
-                    double ar, ai;
-                    if (a.fdouble) {
-                        ar = ((const double *)a.A.p[m])[2 * o];
-                        ai = ((const double *)a.A.p[m])[2 * o + 1];
+        for (int r0 = 0; r0 < a.R; r0 += 4) {
+            double zr[4], zi[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                zr[u] = r0 + u < a.R ? a.lambda[r0 + u] : 0.0;
+                zi[u] = 0.0;
+            }
+#pragma unroll
+            for (int m = 0; m < kMaxOrder; ++m) {
+                if (m >= N) break;
+                double ar[4], ai[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (r0 + u < a.R)
+                        factor_entry(a, m, row[m], r0 + u, ar[u], ai[u]);
+                    else
+                        ar[u] = ai[u] = 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!a.cplx) {
+                        zr[u] *= ar[u];
                     } else {
-                        ar = (double)((const float *)a.A.p[m])[2 * o];
-                        ai = (double)((const float *)a.A.p[m])[2 * o + 1];
+                        const double nr = zr[u] * ar[u] - zi[u] * ai[u], ni = zr[u] * ai[u] + zi[u] * ar[u];
+                        zr[u] = nr;
+                        zi[u] = ni;
                     }
-                    const double nr = zr * ar - zi * ai, ni = zr * ai + zi * ar;
-                    zr = nr;
-                    zi = ni;
                 }
             }
-            mr += zr;
-            mi += zi;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (r0 + u < a.R) {
+                    mr += zr[u];
+                    mi += zi[u];
+                }
         }
         const double dr = xr - mr, di = xi - mi;
         e2 = dr * dr + di * di;
@@ -76,25 +137,32 @@ __global__ __launch_bounds__(kFitThreads) void fit_partial_kernel(FitArgs a) {
     const double s = block_sum<kFitThreads>(e2, sh);
     if (threadIdx.x == 0) {
         a.part[blockIdx.x] = s;
+        s_last = 0;
         if (a.counter) {
             // publish the partial, then let the last block finish (the
             // device-scope fences order the partial stores of every block
             // before the last block's reads, across L2 slices)
             __threadfence();
             const unsigned ticket = atomicAdd(a.counter, 1u);
-            if (ticket == gridDim.x - 1) {
-                __threadfence();
-                const volatile double *vp = a.part;
-                double tot = 0.0;
-                for (unsigned b = 0; b < gridDim.x; ++b) tot += vp[b];
-                const double f = 1.0 - sqrt(a.P * (tot / (double)a.P_hat)) / *a.normX;
-                const uint64_t t = a.t_dev ? *a.t_dev : 0;
-                if (a.fit_out) *a.fit_out = f;
-                if (a.hist) a.hist[t] = f;
-                if (a.hist_host) a.hist_host[t] = f;
-                if (a.t_dev) *a.t_dev = t + 1;
-                *a.counter = 0u;
-            }
+            s_last = ticket == gridDim.x - 1;
+        }
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x < kWave) {
+        __threadfence();
+        const volatile double *vp = a.part;
+        double tot = 0.0;
+        for (unsigned b = threadIdx.x; b < gridDim.x; b += kWave) tot += vp[b];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) tot += __shfl_down(tot, off, kWave);
+        if (threadIdx.x == 0) {
+            const double f = 1.0 - sqrt(a.P * (tot / (double)a.P_hat)) / *a.normX;
+            const uint64_t t = a.t_dev ? *a.t_dev : 0;
+            if (a.fit_out) *a.fit_out = f;
+            if (a.hist) a.hist[t] = f;
+            if (a.hist_host) a.hist_host[t] = f;
+            if (a.t_dev) *a.t_dev = t + 1;
+            *a.counter = 0u;
         }
     }
 }

@@ -56,6 +56,9 @@ hipError_t launch_gather(const GatherPlan &gp, const GatherArgs &a, hipStream_t 
 
 // out[e] = sum_p parts[p*count + e] (fixed order), float or double.
 hipError_t launch_sum_parts(const void *parts, int32_t np, int64_t count, bool dbl, void *out, hipStream_t st);
+// the same sums written as FP64 (inputs FP32 or FP64)
+hipError_t launch_sum_parts_f64(const void *parts, int32_t np, int64_t count, bool in_double, double *out,
+                                hipStream_t st);
 
 // Sum partials into row-major W (In x R, real type) and V (R x R).  For real
 // kinds only (complex ones go through launch_unmix).
@@ -152,7 +155,15 @@ struct FitArgs {
     double *hist;
     double *hist_host;
     uint64_t *t_dev;
+    // Optional cached fit set (the same P-hat entries are used at every
+    // iteration): rows [P_hat][order] and tensor values [P_hat][2] (re, im)
+    // written once by launch_fit_set; when NULL the entries are regenerated
+    // from Philox and loaded from X.
+    const int32_t *frow;
+    const double *fx;
 };
+// Draw the fit set once (rows and tensor values) for FitArgs::frow / fx.
+hipError_t launch_fit_set(const FitArgs &a, int32_t *frow, double *fx, hipStream_t st);
 hipError_t launch_fit_partial(const FitArgs &a, int32_t *nblocks, hipStream_t st);
 // fit_out = 1 - sqrt(P * sum(part)/P_hat) / *normX; also hist[t] (t from t_dev) if hist.
 hipError_t launch_fit_final(const double *part, int32_t nparts, int32_t P_hat, double P,
@@ -165,11 +176,14 @@ hipError_t launch_sqrt_sum(const double *part, int32_t nparts, double *out, hipS
 // ---- proposals and the proposal network (proposal.hip) ------------------------------
 constexpr int kMlpParams = 4545;
 // per-mode stats (doubles): G [R*R], G^{-1} [R*R], |A|_F^2, mean |cosine|
-inline size_t mode_stats_doubles(int R) { return 2 * (size_t)R * R + 2; }
-hipError_t launch_mode_stats(const FactorPtrs &A, const ModeInfo &mi, int32_t R, double *stats, int32_t skip,
-                             hipStream_t st);
-hipError_t launch_marginal_h(const ModeInfo &mi, int32_t R, const double *stats, double *H, hipStream_t st);
-hipError_t launch_row_scores(const FactorPtrs &A, const ModeInfo &mi, int32_t R, const double *stats, const double *H,
+__host__ __device__ inline size_t mode_stats_doubles(int R) { return 2 * (size_t)R * R + 2; }
+// Partial Grams (gpart, gram_part_doubles(order, R) doubles), then per mode
+// m != n: G, G^{-1}, trace and mean |cosine| into stats; with Hinv non-NULL
+// also the inverse of the Hadamard product of the Grams of all modes but n.
+size_t gram_part_doubles(int order, int R);
+hipError_t launch_mode_stats(const FactorPtrs &A, const ModeInfo &mi, int32_t R, double *stats, double *gpart,
+                             double *Hinv, hipStream_t st);
+hipError_t launch_row_scores(const FactorPtrs &A, const ModeInfo &mi, int32_t R, const double *stats, const double *Hinv,
                              const float *params, bool learned, float *const *score, float *feat, float *target,
                              const int64_t *row_off, hipStream_t st);
 // alpha_dev (device) overrides alpha when non-NULL

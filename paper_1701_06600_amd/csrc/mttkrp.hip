@@ -47,7 +47,7 @@ struct Geo {
     static constexpr int RPW = 16 * VE;                    // rows per wave per step
 };
 
-constexpr int kUnroll = 4;  // k-steps (of 4 samples) in flight per iteration
+constexpr int kUnroll = 8;  // k-steps (of 4 samples) whose fiber loads are in flight together
 
 // LDS row stride (in T) for the B operand: >= 16*CT and, for float, an odd
 // multiple of 16 words so that two B rows read by one half-wave hit
@@ -237,7 +237,8 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int sl = ks + 4 * u + lk;
+            if (ks + 4 * u >= ns) break;  // uniform: the rest of this pass is past the chunk
+            const int sl = ks + 4 * u + lk;  // < KC: KC is a multiple of 4 and ns <= KC
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 const T bre = Bre[sl * LDB + ct * 16 + li];
@@ -415,6 +416,28 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const T *parts, int32_t 
     double acc = 0.0;
     for (int p = 0; p < np; ++p) acc += (double)parts[(size_t)p * count + e];
     out[e] = (T)acc;
+}
+
+// out[e] (FP64) = sum over p of parts[p * count + e], in order.
+template <typename T>
+__global__ __launch_bounds__(256) void sum_parts_f64_kernel(const T *parts, int32_t np, int64_t count, double *out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double acc = 0.0;
+    for (int p = 0; p < np; ++p) acc += (double)parts[(size_t)p * count + e];
+    out[e] = acc;
+}
+
+hipError_t launch_sum_parts_f64(const void *parts, int32_t np, int64_t count, bool in_double, double *out,
+                                hipStream_t st) {
+    const int nb = (int)ceil_div(count, 256);
+    if (in_double)
+        hipLaunchKernelGGL(sum_parts_f64_kernel<double>, dim3(nb), dim3(256), 0, st, (const double *)parts, np, count,
+                           out);
+    else
+        hipLaunchKernelGGL(sum_parts_f64_kernel<float>, dim3(nb), dim3(256), 0, st, (const float *)parts, np, count,
+                           out);
+    return hipGetLastError();
 }
 
 hipError_t launch_sum_parts(const void *parts, int32_t np, int64_t count, bool dbl, void *out, hipStream_t st) {

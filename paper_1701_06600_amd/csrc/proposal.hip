@@ -29,65 +29,125 @@ constexpr float kFeatEps = 1e-6f;
 // ---------------------------------------------------------------------------
 // Per-mode statistics: G = A^T A (FP64), G^{-1}, |A|_F^2, mean |cosine|.
 // stats layout per mode (doubles): G [R*R], Ginv [R*R], frob2, cong.
-__global__ __launch_bounds__(256) void mode_stats_kernel(FactorPtrs A, ModeInfo mi, int32_t R, double *stats,
-                                                         int32_t skip) {
+//
+// (1) gram_part_kernel: block (c, m) sums a_i a_i^T over chunk c of the
+//     rows of A^(m) (at most kGramChunks chunks per mode), staging tiles of
+//     kGramTile rows in LDS; upper triangle computed, mirrored on store.
+// (2) stats_finish_kernel: block m != n adds the chunk partials in chunk
+//     order, writes G, its trace and mean |cosine|, and inverts it; block n
+//     (the mode of the step, otherwise idle) forms the Hadamard product of
+//     the Grams of all modes but n and writes its inverse to Hinv (only
+//     when Hinv is requested: the exact marginals need it).
+constexpr int kGramChunks = 64, kGramTile = 64, kStatThreads = 256;
+
+__global__ __launch_bounds__(kStatThreads) void gram_part_kernel(FactorPtrs A, ModeInfo mi, int32_t R,
+                                                                  double *gpart) {
+    __shared__ double tile[kGramTile][kMaxRank + 1];
+    const int m = blockIdx.y, c = blockIdx.x, tid = threadIdx.x;
+    if (m == mi.n) return;
+    const int64_t I = mi.dims[m];
+    const int nch = (int)min((int64_t)kGramChunks, ceil_div(I, kGramTile));
+    if (c >= nch) return;
+    const int64_t per = ceil_div(I, nch);
+    const int64_t i0 = (int64_t)c * per, i1 = min(I, i0 + per);
+    const float *a = (const float *)A.p[m];
+    constexpr int kQ = kMaxRank * kMaxRank / kStatThreads;
+    double acc[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) acc[q] = 0.0;
+    for (int64_t t0 = i0; t0 < i1; t0 += kGramTile) {
+        const int nr = (int)min((int64_t)kGramTile, i1 - t0);
+        __syncthreads();
+        for (int e = tid; e < nr * R; e += kStatThreads) {
+            const int rr = e / R, cc = e - rr * R;
+            tile[rr][cc] = (double)a[(t0 + rr) * R + cc];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int e = tid + q * kStatThreads;
+            const int r = e / R, s2 = e - r * R;
+            if (e < R * R && r <= s2) {
+                double v = acc[q];
+                for (int rr = 0; rr < nr; ++rr) v += tile[rr][r] * tile[rr][s2];
+                acc[q] = v;
+            }
+        }
+    }
+    double *gp = gpart + ((size_t)m * kGramChunks + c) * R * R;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int e = tid + q * kStatThreads;
+        const int r = e / R, s2 = e - r * R;
+        if (e < R * R && r <= s2) {
+            gp[r * R + s2] = acc[q];
+            gp[s2 * R + r] = acc[q];
+        }
+    }
+}
+
+// Chunk partials of entry e, added in chunk order; loads issued eight at a time.
+__device__ inline double gram_sum(const double *gpart, int m, int nch, int R, int e) {
+    const double *gp = gpart + (size_t)m * kGramChunks * R * R + e;
+    const size_t st = (size_t)R * R;
+    double g = 0.0;
+    int c = 0;
+    for (; c + 8 <= nch; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = gp[(c + k) * st];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g += v[k];
+    }
+    for (; c < nch; ++c) g += gp[c * st];
+    return g;
+}
+
+__global__ __launch_bounds__(kStatThreads) void stats_finish_kernel(ModeInfo mi, int32_t R, const double *gpart,
+                                                                     double *stats, double *Hinv) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const int m = blockIdx.x;
-    if (m == skip) return;
+    __shared__ double s_red[kStatThreads / kWave];
+    const int m = blockIdx.x, n = mi.n, N = mi.order, tid = threadIdx.x;
+    const bool hblock = (m == n);
+    if (hblock && !Hinv) return;
     const int ld = R + 1;
     double *B1 = (double *)lds, *B2 = B1 + R * ld, *B3 = B2 + R * ld, *cs = B3 + R * ld, *tmp = cs + 66;
     int *pairs = (int *)(tmp + kMaxRank);
-    const float *a = (const float *)A.p[m];
-    const int64_t I = mi.dims[m];
-    for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
-        const int r = e / R, s = e - r * R;
-        double acc = 0.0;
-        for (int64_t i = 0; i < I; ++i) acc += (double)a[i * R + r] * (double)a[i * R + s];
-        B1[r * ld + s] = acc;
-        B3[r * ld + s] = acc;
-    }
-    __syncthreads();
-    double *st = stats + (size_t)m * (2 * R * R + 2);
-    for (int e = threadIdx.x; e < R * R; e += blockDim.x) st[e] = B3[(e / R) * ld + e % R];
-    if (threadIdx.x == 0) {
-        double fr = 0.0, cg = 0.0;
-        for (int r = 0; r < R; ++r) fr += B3[r * ld + r];
-        for (int r = 0; r < R; ++r)
-            for (int s = 0; s < R; ++s)
-                if (r != s) cg += fabs(B3[r * ld + s]) / sqrt(B3[r * ld + r] * B3[s * ld + s]);
-        st[2 * R * R] = fr;
-        st[2 * R * R + 1] = R > 1 ? cg / ((double)R * (R - 1)) : 0.0;
-    }
-    spd_inverse(B1, B2, B3, tmp, R, ld, cs, pairs);
-    for (int e = threadIdx.x; e < R * R; e += blockDim.x) st[R * R + e] = B1[(e / R) * ld + e % R];
-}
-
-// H_m = inverse(Hadamard of the Grams in K) * Hadamard of the Grams in K\{m},
-// for every m in K (K = all modes but n).  One workgroup.
-__global__ __launch_bounds__(256) void marginal_h_kernel(ModeInfo mi, int32_t R, const double *stats, double *H) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    const int ld = R + 1, n = mi.n, N = mi.order;
-    double *B1 = (double *)lds, *B2 = B1 + R * ld, *B3 = B2 + R * ld, *cs = B3 + R * ld, *tmp = cs + 66;
-    int *pairs = (int *)(tmp + kMaxRank);
-    const size_t sz = 2 * (size_t)R * R + 2;
-    for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
-        double g = 1.0;
-        for (int k = 0; k < N; ++k)
-            if (k != n) g *= stats[k * sz + e];
+    for (int e = tid; e < R * R; e += kStatThreads) {
+        double g;
+        if (!hblock) {
+            g = gram_sum(gpart, m, (int)min((int64_t)kGramChunks, ceil_div(mi.dims[m], kGramTile)), R, e);
+        } else {
+            g = 1.0;
+            for (int k = 0; k < N; ++k)
+                if (k != n) g *= gram_sum(gpart, k, (int)min((int64_t)kGramChunks, ceil_div(mi.dims[k], kGramTile)), R, e);
+        }
         B1[(e / R) * ld + e % R] = g;
         B3[(e / R) * ld + e % R] = g;
     }
     __syncthreads();
-    spd_inverse(B1, B2, B3, tmp, R, ld, cs, pairs);
-    for (int m = 0; m < N; ++m) {
-        if (m == n) continue;
-        for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
-            double h = B1[(e / R) * ld + e % R];
-            for (int k = 0; k < N; ++k)
-                if (k != n && k != m) h *= stats[k * sz + e];
-            H[(size_t)m * R * R + e] = h;
+    double *st = stats + (size_t)m * mode_stats_doubles(R);
+    if (!hblock) {
+        double fr = 0.0, cg = 0.0;
+        for (int e = tid; e < R * R; e += kStatThreads) {
+            const int r = e / R, s2 = e - r * R;
+            const double v = B3[r * ld + s2];
+            st[e] = v;
+            if (r == s2)
+                fr += v;
+            else
+                cg += fabs(v) / sqrt(B3[r * ld + r] * B3[s2 * ld + s2]);
+        }
+        fr = block_sum_dyn(fr, s_red);
+        cg = block_sum_dyn(cg, s_red);
+        if (tid == 0) {
+            st[2 * R * R] = fr;
+            st[2 * R * R + 1] = R > 1 ? cg / ((double)R * (R - 1)) : 0.0;
         }
     }
+    spd_inverse<kMaxRank * kMaxRank / kStatThreads>(B1, B2, B3, tmp, R, ld, cs, pairs);
+    double *out = hblock ? Hinv : st + R * R;
+    for (int e = tid; e < R * R; e += kStatThreads) out[e] = B1[(e / R) * ld + e % R];
 }
 
 // ---------------------------------------------------------------------------
@@ -112,13 +172,16 @@ __device__ inline float mlp_row(const float *P, const float x[4]) {
 
 // Row scores for every mode m != n: mode == LEARNED: the network's logit;
 // mode == MARGINAL: log of the exact marginal.  Also (optionally) writes the
-// feature rows and the exact targets L/R for training.
+// feature rows and the exact targets L/R for training.  One wave per
+// kScoreRows rows: G^{-1}, the marginal matrix H_m = Hinv * prod_{k in
+// K\{m}} G_k (Hadamard products), the rows (transposed) and the network
+// are staged in LDS, and each lane evaluates the quadratic forms of its row.
 struct RowArgs {
     FactorPtrs A;
     ModeInfo mi;
     int32_t R;
     const double *stats;
-    const double *H;        // marginal matrices (may be NULL when not needed)
+    const double *Hinv;     // inverse of the Hadamard product of the Grams in K (NULL: no marginals)
     const float *params;    // network (LEARNED)
     int32_t learned;
     float *score[kMaxOrder];  // per mode, I_m floats
@@ -127,53 +190,130 @@ struct RowArgs {
     int64_t row_off[kMaxOrder];  // first row of mode m in feat/target
 };
 
-__global__ __launch_bounds__(256) void row_scores_kernel(RowArgs a) {
-    __shared__ float P[kParams];
-    __shared__ double s_f4[kMaxOrder];
-    const int m = blockIdx.y;
-    if (m == a.mi.n) return;
-    const int R = a.R, N = a.mi.order;
-    const size_t sz = 2 * (size_t)R * R + 2;
-    if (a.learned)
-        for (int e = threadIdx.x; e < kParams; e += blockDim.x) P[e] = a.params[e];
-    if (threadIdx.x == 0) {
-        double c = 0.0;
-        int cnt = 0;
-        for (int k = 0; k < N; ++k)
-            if (k != a.mi.n && k != m) {
-                c += a.stats[k * sz + 2 * R * R + 1];
-                ++cnt;
+constexpr int kScoreRows = 128, kScoreThreads = 128;
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline int pad16(int R) { return (R + 15) & ~15; }
+
+size_t row_scores_lds(int R, bool marg, bool learned) {
+    const size_t RP = pad16(R);
+    size_t b = sizeof(double) * (RP * RP * (marg ? 2 : 1) + R + 2 * kScoreRows) + sizeof(float) * RP * kScoreRows;
+    if (learned) b += sizeof(float) * kParams;
+    return b;
+}
+
+// Quadratic forms q_i = a_i^T M a_i for the block's rows: U = A_rows M on
+// FP64 MFMA 16x16x4 (lane l: A operand A[l%16][l/16], B operand
+// M[l/16][l%16], result U[l/16 + 4v][l%16]), then the row sums of U * A by
+// shuffles over the 16 lanes that share a row, in a fixed order.
+__device__ inline void quad_forms(const float *sRow, const double *M1, const double *M2, int RP, int nr, double *q1,
+                                  double *q2) {
+    const int w = threadIdx.x / kWave, l = threadIdx.x & (kWave - 1), li = l & 15, lk = l >> 4;
+    for (int rt = 0; rt < 4; ++rt) {
+        const int rb = w * 64 + rt * 16;
+        if (rb >= nr) break;
+        double p1[4] = {0.0, 0.0, 0.0, 0.0}, p2[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int ct = 0; ct < RP; ct += 16) {
+            v4d_t u1 = {0.0, 0.0, 0.0, 0.0}, u2 = {0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < RP; k0 += 4) {
+                const int k = k0 + lk;
+                const double av = (double)sRow[k * kScoreRows + rb + li];
+                u1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, M1[k * RP + ct + li], u1, 0, 0, 0);
+                if (M2) u2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, M2[k * RP + ct + li], u2, 0, 0, 0);
             }
-        s_f4[0] = cnt ? c / cnt : 0.0;
-    }
-    __syncthreads();
-    const int64_t I = a.mi.dims[m];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= I) return;
-    const float *row = (const float *)a.A.p[m] + i * R;
-    const double *G = a.stats + m * sz, *Gi = G + R * R;
-    const double frob2 = G[2 * R * R];
-    double rn = 0.0, lev = 0.0, cn = 0.0, marg = 0.0;
-    for (int r = 0; r < R; ++r) {
-        const double ar = (double)row[r];
-        rn += ar * ar;
-        cn += ar * ar / G[r * R + r];
-        double gr = 0.0, hr = 0.0;
-        for (int s = 0; s < R; ++s) {
-            gr += Gi[r * R + s] * (double)row[s];
-            if (a.H) hr += a.H[(size_t)m * R * R + r * R + s] * (double)row[s];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double ar = (double)sRow[(ct + li) * kScoreRows + rb + lk + 4 * v];
+                p1[v] += u1[v] * ar;
+                p2[v] += u2[v] * ar;
+            }
         }
-        lev += ar * gr;
-        marg += ar * hr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                p1[v] += __shfl_xor(p1[v], off, kWave);
+                p2[v] += __shfl_xor(p2[v], off, kWave);
+            }
+            if (li == 0) {
+                q1[rb + lk + 4 * v] = p1[v];
+                q2[rb + lk + 4 * v] = p2[v];
+            }
+        }
     }
+}
+
+__global__ __launch_bounds__(kScoreThreads) void row_scores_kernel(RowArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int m = blockIdx.y, tid = threadIdx.x;
+    if (m == a.mi.n) return;
+    const int R = a.R, N = a.mi.order, RP = pad16(R);
+    const int64_t I = a.mi.dims[m];
+    const int64_t r0 = (int64_t)blockIdx.x * kScoreRows;
+    if (r0 >= I) return;
+    const bool marg = a.Hinv != nullptr;
+    const size_t sz = mode_stats_doubles(R);
+    double *sGi = (double *)lds;                  // [RP][RP], zero padded
+    double *sH = sGi + RP * RP;                   // [RP][RP] (marginals only)
+    double *sGd = sH + (marg ? RP * RP : 0);      // [R]
+    double *sLev = sGd + R;                       // [kScoreRows]
+    double *sMg = sLev + kScoreRows;              // [kScoreRows]
+    float *sRow = (float *)(sMg + kScoreRows);    // [RP][kScoreRows], zero padded
+    float *P = sRow + RP * kScoreRows;
+    const double *G = a.stats + m * sz, *Gi = G + R * R;
+    for (int e = tid; e < RP * RP; e += kScoreThreads) {
+        const int r = e / RP, c = e - r * RP;
+        const bool in = r < R && c < R;
+        sGi[e] = in ? Gi[r * R + c] : 0.0;
+        if (marg) {
+            double h = 0.0;
+            if (in) {
+                h = a.Hinv[r * R + c];
+                for (int k = 0; k < N; ++k)
+                    if (k != a.mi.n && k != m) h *= a.stats[k * sz + r * R + c];
+            }
+            sH[e] = h;
+        }
+    }
+    for (int r = tid; r < R; r += kScoreThreads) sGd[r] = G[r * R + r];
+    if (a.learned)
+        for (int e = tid; e < kParams; e += kScoreThreads) P[e] = a.params[e];
+    const int nr = (int)min((int64_t)kScoreRows, I - r0);
+    for (int e = tid; e < RP * kScoreRows; e += kScoreThreads) sRow[e] = 0.f;
+    __syncthreads();
+    const float *A = (const float *)a.A.p[m] + r0 * R;
+    for (int e = tid; e < nr * R; e += kScoreThreads) {
+        const int rr = e / R, c = e - rr * R;
+        sRow[c * kScoreRows + rr] = A[e];
+    }
+    double f4 = 0.0;
+    int cnt = 0;
+    for (int k = 0; k < N; ++k)
+        if (k != a.mi.n && k != m) {
+            f4 += a.stats[k * sz + 2 * R * R + 1];
+            ++cnt;
+        }
+    f4 = cnt ? f4 / cnt : 0.0;
+    __syncthreads();
+    quad_forms(sRow, sGi, marg ? sH : nullptr, RP, nr, sLev, sMg);
+    __syncthreads();
+    if (tid >= nr) return;
+    const int64_t i = r0 + tid;
+    const double frob2 = G[2 * R * R];
+    double rn = 0.0, cn = 0.0;
+    for (int r = 0; r < R; ++r) {
+        const double ar = (double)sRow[r * kScoreRows + tid];
+        rn += ar * ar;
+        cn += ar * ar / sGd[r];
+    }
+    const double lev = sLev[tid], mg = marg ? sMg[tid] : 0.0;
     const double f1 = (double)I * rn / frob2, f2 = (double)I / R * lev, f3 = (double)I / R * cn;
-    float x[4] = {logf((float)f1 + kFeatEps), logf((float)f2 + kFeatEps), logf((float)f3 + kFeatEps),
-                  (float)s_f4[0]};
+    float x[4] = {logf((float)f1 + kFeatEps), logf((float)f2 + kFeatEps), logf((float)f3 + kFeatEps), (float)f4};
     float sc;
     if (a.learned)
         sc = mlp_row(P, x);
     else
-        sc = logf((float)fmax(marg, 1e-30));
+        sc = logf((float)fmax(mg, 1e-30));
     if (a.score[m]) a.score[m][i] = sc;
     if (a.feat) {
         float *f = a.feat + (a.row_off[m] + i) * 4;
@@ -182,7 +322,7 @@ __global__ __launch_bounds__(256) void row_scores_kernel(RowArgs a) {
         f[2] = x[2];
         f[3] = x[3];
     }
-    if (a.target) a.target[a.row_off[m] + i] = (float)(marg / R);
+    if (a.target) a.target[a.row_off[m] + i] = (float)(mg / R);
 }
 
 // Per mode m != n: p = softmax(score), mixture (1-alpha) p + alpha/I,
@@ -192,66 +332,59 @@ struct ScoreCdf {
     uint64_t *cdf[kMaxOrder];
 };
 
-__global__ __launch_bounds__(256) void cdf_kernel(ModeInfo mi, ScoreCdf sc, double alpha_val, const double *alpha_dev) {
-    __shared__ float s_red[256];
-    __shared__ uint64_t s_scan[256];
+constexpr int kCdfThreads = 256;
+
+__global__ __launch_bounds__(kCdfThreads) void cdf_kernel(ModeInfo mi, ScoreCdf sc, double alpha_val,
+                                                          const double *alpha_dev) {
+    __shared__ double s_red[kCdfThreads / kWave];
+    __shared__ float s_mx[kCdfThreads / kWave];
+    __shared__ uint64_t s_wsum[kCdfThreads / kWave];
     const int m = blockIdx.x;
     if (m == mi.n) return;
     const int64_t I = mi.dims[m];
     const float *z = sc.score[m];
     uint64_t *c = sc.cdf[m];
     const double alpha = alpha_dev ? *alpha_dev : alpha_val;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    constexpr int nw = kCdfThreads / kWave;
+    // max of the scores
     float mx = -INFINITY;
-    for (int64_t i = tid; i < I; i += nt) mx = fmaxf(mx, z[i]);
-    s_red[tid] = mx;
+    for (int64_t i = tid; i < I; i += kCdfThreads) mx = fmaxf(mx, z[i]);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
+    if (lane == 0) s_mx[wid] = mx;
     __syncthreads();
-    for (int o = nt / 2; o > 0; o >>= 1) {
-        if (tid < o) s_red[tid] = fmaxf(s_red[tid], s_red[tid + o]);
-        __syncthreads();
-    }
-    mx = s_red[0];
-    __syncthreads();
+    mx = s_mx[0];
+    for (int w = 1; w < nw; ++w) mx = fmaxf(mx, s_mx[w]);
+    // softmax normaliser, fixed order
     double sum = 0.0;
-    for (int64_t i = tid; i < I; i += nt) sum += exp((double)z[i] - (double)mx);
-    __shared__ double s_sum[256];
-    s_sum[tid] = sum;
-    __syncthreads();
-    if (tid == 0) {
-        double s = 0.0;
-        for (int t = 0; t < nt; ++t) s += s_sum[t];
-        s_sum[0] = s;
-    }
-    __syncthreads();
-    const double tot = s_sum[0];
-    // contiguous chunk per thread, then an exclusive scan of the chunk sums
-    const int64_t per = ceil_div(I, nt);
+    for (int64_t i = tid; i < I; i += kCdfThreads) sum += exp((double)z[i] - (double)mx);
+    const double tot = block_sum_dyn(sum, s_red);
+    // contiguous chunk per thread, integer weights, exclusive scan of the chunk sums
+    const int64_t per = ceil_div(I, kCdfThreads);
     const int64_t i0 = tid * per, i1 = min(I, i0 + per);
+    auto qof = [&](int64_t i) {
+        const double p = (1.0 - alpha) * exp((double)z[i] - (double)mx) / tot + alpha / (double)I;
+        double q = floor(p * 4294967296.0);
+        q = fmin(fmax(q, 1.0), 4294967295.0);
+        return (uint64_t)q;
+    };
     uint64_t local = 0;
-    for (int64_t i = i0; i < i1; ++i) {
-        const double p = (1.0 - alpha) * exp((double)z[i] - (double)mx) / tot + alpha / (double)I;
-        double q = floor(p * 4294967296.0);
-        q = fmin(fmax(q, 1.0), 4294967295.0);
-        local += (uint64_t)q;
+    for (int64_t i = i0; i < i1; ++i) local += qof(i);
+    uint64_t incl = local;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t v = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += v;
     }
-    s_scan[tid] = local;
+    if (lane == kWave - 1) s_wsum[wid] = incl;
     __syncthreads();
-    if (tid == 0) {
-        uint64_t run = 0;
-        for (int t = 0; t < nt; ++t) {
-            const uint64_t v = s_scan[t];
-            s_scan[t] = run;
-            run += v;
-        }
-        c[0] = 0;
-    }
-    __syncthreads();
-    uint64_t run = s_scan[tid];
+    uint64_t base = 0;
+    for (int w = 0; w < wid; ++w) base += s_wsum[w];
+    uint64_t run = base + incl - local;
+    if (tid == 0) c[0] = 0;
     for (int64_t i = i0; i < i1; ++i) {
-        const double p = (1.0 - alpha) * exp((double)z[i] - (double)mx) / tot + alpha / (double)I;
-        double q = floor(p * 4294967296.0);
-        q = fmin(fmax(q, 1.0), 4294967295.0);
-        run += (uint64_t)q;
+        run += qof(i);
         c[i + 1] = run;
     }
 }
@@ -412,26 +545,25 @@ static size_t inv_lds(int R) {
     return sizeof(double) * ((size_t)3 * R * ld + 66 + kMaxRank) + sizeof(int) * 68;
 }
 
-hipError_t launch_mode_stats(const FactorPtrs &A, const ModeInfo &mi, int32_t R, double *stats, int32_t skip,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(mode_stats_kernel, dim3(mi.order), dim3(256), inv_lds(R), st, A, mi, R, stats, skip);
+size_t gram_part_doubles(int order, int R) { return (size_t)order * kGramChunks * R * R; }
+
+hipError_t launch_mode_stats(const FactorPtrs &A, const ModeInfo &mi, int32_t R, double *stats, double *gpart,
+                             double *Hinv, hipStream_t st) {
+    hipLaunchKernelGGL(gram_part_kernel, dim3(kGramChunks, mi.order), dim3(kStatThreads), 0, st, A, mi, R, gpart);
+    hipLaunchKernelGGL(stats_finish_kernel, dim3(mi.order), dim3(kStatThreads), inv_lds(R), st, mi, R,
+                       (const double *)gpart, stats, Hinv);
     return hipGetLastError();
 }
 
-hipError_t launch_marginal_h(const ModeInfo &mi, int32_t R, const double *stats, double *H, hipStream_t st) {
-    hipLaunchKernelGGL(marginal_h_kernel, dim3(1), dim3(256), inv_lds(R), st, mi, R, stats, H);
-    return hipGetLastError();
-}
-
-hipError_t launch_row_scores(const FactorPtrs &A, const ModeInfo &mi, int32_t R, const double *stats, const double *H,
-                             const float *params, bool learned, float *const *score, float *feat, float *target,
-                             const int64_t *row_off, hipStream_t st) {
+hipError_t launch_row_scores(const FactorPtrs &A, const ModeInfo &mi, int32_t R, const double *stats,
+                             const double *Hinv, const float *params, bool learned, float *const *score, float *feat,
+                             float *target, const int64_t *row_off, hipStream_t st) {
     RowArgs a{};
     a.A = A;
     a.mi = mi;
     a.R = R;
     a.stats = stats;
-    a.H = H;
+    a.Hinv = Hinv;
     a.params = params;
     a.learned = learned ? 1 : 0;
     int64_t maxI = 1;
@@ -442,8 +574,9 @@ hipError_t launch_row_scores(const FactorPtrs &A, const ModeInfo &mi, int32_t R,
     }
     a.feat = feat;
     a.target = target;
-    dim3 grid((unsigned)ceil_div(maxI, 256), mi.order);
-    hipLaunchKernelGGL(row_scores_kernel, grid, dim3(256), 0, st, a);
+    dim3 grid((unsigned)ceil_div(maxI, kScoreRows), mi.order);
+    hipLaunchKernelGGL(row_scores_kernel, grid, dim3(kScoreThreads), row_scores_lds(R, Hinv != nullptr, learned), st,
+                       a);
     return hipGetLastError();
 }
 
@@ -454,7 +587,7 @@ hipError_t launch_cdf(const ModeInfo &mi, float *const *score, double alpha, con
         sc.score[m] = score[m];
         sc.cdf[m] = cdf[m];
     }
-    hipLaunchKernelGGL(cdf_kernel, dim3(mi.order), dim3(256), 0, st, mi, sc, alpha, alpha_dev);
+    hipLaunchKernelGGL(cdf_kernel, dim3(mi.order), dim3(kCdfThreads), 0, st, mi, sc, alpha, alpha_dev);
     return hipGetLastError();
 }
 
