@@ -46,7 +46,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--layout", type=int, default=1, help="0: mode-major copies of X-hat, 1: strided gathers")
+    ap.add_argument("--layout", type=int, default=0, help="0: mode-major copies of X-hat, 1: strided gathers")
     ap.add_argument("--legs", default="main,precision,learned")
     ap.add_argument("--train-instances", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -77,6 +77,8 @@ struct cprand_plan {
     double *hist_host = nullptr;
     void *wtmp = nullptr;   // maxdim x R doubles: summed (or unmixed) MTTKRP of the split path
     double *vsum = nullptr; // R x R: summed Gram of the split path
+    void *snapbuf[2] = {};   // factors + lambda after even / odd iterations (run-ahead loop)
+    size_t snapbytes = 0;
     int32_t *frow = nullptr; // the fixed fit set: rows [P_hat][N] and tensor values [P_hat][2]
     double *fx = nullptr;
     void *ysum = nullptr;
@@ -364,7 +366,23 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
     fa.frow = p->frow;
     fa.fx = p->fx;
     int32_t nb = 0;
-    return launch_fit_partial(fa, &nb, st);
+    e = launch_fit_partial(fa, &nb, st);
+    if (e == hipSuccess && !p->adaptive) {
+        SnapArgs sa{};
+        const size_t tsz = p->dbl ? 8 : 4;
+        for (int m = 0; m < N; ++m) {
+            sa.src[m] = p->fac[m];
+            sa.words[m] = (int64_t)(p->dims[m] * R * tsz / 4);
+        }
+        sa.nsrc = N;
+        sa.lambda = p->lambda;
+        sa.R = R;
+        sa.dst0 = p->snapbuf[0];
+        sa.dst1 = p->snapbuf[1];
+        sa.t_dev = p->t_dev;
+        e = launch_snapshot(sa, st);
+    }
+    return e;
 }
 
 }  // namespace
@@ -529,6 +547,12 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     if (e == hipSuccess) e = dalloc(p, &p->wtmp, (size_t)maxdim * R * 8);
     if (e == hipSuccess) e = dalloc(p, (void **)&p->vsum, (size_t)R * R * 8);
     if (e == hipSuccess) e = dalloc(p, (void **)&p->frow, (size_t)o.P_hat * N * 4);
+    if (e == hipSuccess) {
+        p->snapbytes = (size_t)R * 8;
+        for (int m = 0; m < N; ++m) p->snapbytes += (size_t)p->dims[m] * R * tsz;
+        e = dalloc(p, &p->snapbuf[0], p->snapbytes);
+        if (e == hipSuccess) e = dalloc(p, &p->snapbuf[1], p->snapbytes);
+    }
     if (e == hipSuccess) e = dalloc(p, (void **)&p->fx, (size_t)o.P_hat * 16);
     if (e == hipSuccess && p->mix) e = dalloc(p, &p->ysum, (size_t)maxdim * 2 * R * tsz);
     p->adaptive = o.proposal == CPRAND_PROPOSAL_LEARNED || o.proposal == CPRAND_PROPOSAL_MARGINAL;
@@ -733,7 +757,48 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
     int level = 0, worse = 0, fell_back = 0;
     double best = -INFINITY;
     std::vector<int> levels;
-    for (; it < p->o.max_iters; ++it) {
+    if (!p->adaptive) {
+        // One iteration ahead: iteration t+1 is launched before the host reads
+        // F-hat of iteration t; every iteration ends by saving the factors and
+        // lambda (buffer t mod 2), so a stop at t restores exactly that state.
+        auto launch_one = [&](int t) {
+            hipError_t r = exec ? hipGraphLaunch(exec, st) : enqueue_iteration(p, X->data, contig_x, st);
+            if (r == hipSuccess) r = hipEventRecord(p->ev[t & 1 ? 3 : 2], st);
+            return r;
+        };
+        bool ahead = false;
+        e = launch_one(0);
+        for (; e == hipSuccess && it < p->o.max_iters; ++it) {
+            ahead = it + 1 < p->o.max_iters;
+            if (ahead) e = launch_one(it + 1);
+            if (e == hipSuccess) e = hipEventSynchronize(p->ev[it & 1 ? 3 : 2]);
+            if (e != hipSuccess) break;
+            F = p->hist_host[it];
+            if (!isfinite(F)) {
+                e = hipErrorUnknown;
+                break;
+            }
+            levels.push_back(0);
+            if (stop(it, F)) {
+                ++it;
+                break;
+            }
+            ahead = false;
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess && ahead) {  // undo the iteration launched past the stop
+            const char *sb = (const char *)p->snapbuf[(it - 1) & 1];
+            const size_t tsz = p->dbl ? 8 : 4;
+            size_t off = 0;
+            for (int m = 0; m < N && e == hipSuccess; ++m) {
+                const size_t b = (size_t)p->dims[m] * R * tsz;
+                e = hipMemcpyAsync(p->fac[m], sb + off, b, hipMemcpyDeviceToDevice, st);
+                off += b;
+            }
+            if (e == hipSuccess) e = hipMemcpyAsync(p->lambda, sb + off, (size_t)R * 8, hipMemcpyDeviceToDevice, st);
+        }
+    }
+    for (; p->adaptive && it < p->o.max_iters; ++it) {
         const bool duel = p->adaptive && level < 2 && it > 0 && ((it + 1) & it) == 0;
         if (duel) e = save(SNAP_PRE);
         if (e == hipSuccess) e = run_iteration();

@@ -258,6 +258,27 @@ __global__ void fill_u64_kernel(uint64_t *p, uint64_t v) {
 __global__ void inc_u64_kernel(uint64_t *p) {
     if (threadIdx.x == 0) *p += 1;
 }
+// Copy the factors and lambda after an outer iteration into one of two
+// buffers, chosen by the iteration just finished ((*t_dev - 1) mod 2): the
+// loop can launch the next iteration before it reads this one's fit estimate.
+__global__ __launch_bounds__(256) void snapshot_kernel(SnapArgs a) {
+    const uint64_t t = *a.t_dev - 1;
+    uint32_t *dst = (uint32_t *)(t & 1 ? a.dst1 : a.dst0);
+    int64_t off = 0;
+    for (int m = 0; m <= a.nsrc; ++m) {
+        const uint32_t *src = (const uint32_t *)(m < a.nsrc ? a.src[m] : (const void *)a.lambda);
+        const int64_t w = m < a.nsrc ? a.words[m] : 2 * (int64_t)a.R;
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < w; e += (int64_t)gridDim.x * blockDim.x)
+            dst[off + e] = src[e];
+        off += w;
+    }
+}
+
+hipError_t launch_snapshot(const SnapArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(snapshot_kernel, dim3(32), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, hipStream_t st) {
     hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, p, v);
     return hipGetLastError();

@@ -203,6 +203,16 @@ hipError_t launch_layout_copy(const ModeInfo &xi, const void *X, int xkind, int3
 
 // ---- small helpers ---------------------------------------------------------------------
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, hipStream_t st);
+struct SnapArgs {
+    const void *src[kMaxOrder];   // factors (4-byte words each: words[m])
+    int64_t words[kMaxOrder];
+    int32_t nsrc;
+    const double *lambda;         // R doubles, stored after the factors
+    int32_t R;
+    void *dst0, *dst1;            // by the parity of the iteration just finished
+    const uint64_t *t_dev;
+};
+hipError_t launch_snapshot(const SnapArgs &a, hipStream_t st);
 hipError_t launch_inc_u64(uint64_t *p, hipStream_t st);
 
 }  // namespace cprand

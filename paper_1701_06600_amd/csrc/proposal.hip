@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kStatThreads) void stats_finish_kernel(ModeInfo mi,
             st[2 * R * R + 1] = R > 1 ? cg / ((double)R * (R - 1)) : 0.0;
         }
     }
-    spd_inverse<kMaxRank * kMaxRank / kStatThreads>(B1, B2, B3, tmp, R, ld, cs, pairs);
+    spd_inverse(B1, B2, B3, tmp, R, ld, cs, pairs);
     double *out = hblock ? Hinv : st + R * R;
     for (int e = tid; e < R * R; e += kStatThreads) out[e] = B1[(e / R) * ld + e % R];
 }

@@ -50,9 +50,7 @@ __global__ __launch_bounds__(NT) void solve_kernel(SolveArgs a) {
         Ws[ii * ld + r] = acc;
     }
     __syncthreads();
-    // NT = 64 is launched only for R <= 16 (R^2 <= 4 * 64)
-    constexpr int kQ = NT == 64 ? 4 : (kMaxRank * kMaxRank + NT - 1) / NT;
-    const int failed = spd_inverse<kQ>(B1, B2, B3, A0, R, ld, cs, pairs);
+    const int failed = spd_inverse(B1, B2, B3, A0, R, ld, cs, pairs);
     if (tid == 0 && blockIdx.x == 0 && a.info) {
         if (failed)
             *a.info = CPRAND_W_PINV;

@@ -5,8 +5,9 @@
 // V is inverted in place by Gauss-Jordan elimination without pivoting (the
 // pivots of a symmetric positive definite matrix are the diagonal entries of
 // its successive Schur complements, the squares of its Cholesky diagonal):
-// R steps, each a parallel rank-one update of all R^2 entries between two
-// barriers.  If a pivot falls below 1e-12 of the largest diagonal entry of V,
+// for R <= 16 by one wave in registers (R steps, shuffles between lanes, no
+// barriers), above that blocked by 4 (ceil(R / 4) steps, each a rank-4
+// update of the whole matrix between two barriers).  If a pivot falls below 1e-12 of the largest diagonal entry of V,
 // V is diagonalised by parallel cyclic Jacobi rotations (round-robin
 // pairing, R/2 disjoint rotations per step) and inverted on its eigenvalues
 // above 1e-12 of the largest: the pseudo-inverse, which gives the
@@ -36,7 +37,7 @@ __device__ inline double block_sum_dyn(double v, double *sh) {
 
 // Jacobi eigen-decomposition of the symmetric M (stride ld) with
 // eigenvectors accumulated in Q; on exit diag(M) holds the eigenvalues.
-__device__ inline void jacobi_eig(double *M, double *Q, int R, int ld, double *cs, int *pairs) {
+__device__ __forceinline__ void jacobi_eig(double *M, double *Q, int R, int ld, double *cs, int *pairs) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int Rp = R + (R & 1);
     __shared__ double s_red[16];
@@ -134,55 +135,10 @@ __device__ inline double diag_absmax(const double *M, int R, int ld, int *bad) {
     return s_mx;
 }
 
-// Orders the LDS accesses of one wavefront: its lanes run in lockstep, so a
-// fence at wavefront scope is all that separates a write from the reads of
-// other lanes.
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Exact select by bit masks (keeps the elimination step free of branches).
 __device__ inline double bsel(bool c, double a, double b) {
     const long long m = -(long long)c;
     return __longlong_as_double((__double_as_longlong(a) & m) | (__double_as_longlong(b) & ~m));
-}
-
-// One Gauss-Jordan step on pivot k for the entries a thread keeps in
-// registers (v[q] at row ii[q], column jj[q]; valid[q] false for padding
-// slots), given col[i] = M(i, k), rowp[j] = M(k, j) / M(k, k) and
-// inv = 1 / M(k, k):  M(k, k) <- inv, M(k, j) <- rowp[j], M(i, k) <- -col[i] inv,
-// M(i, j) <- M(i, j) - col[i] rowp[j].  Every candidate is computed and the
-// right one selected; the new values are also stored to M (stride ld).
-template <int Q>
-__device__ inline void gj_update(double *v, const int *ii, const int *jj, const bool *valid, int k, double inv,
-                                 const double *col, const double *rowp, double *M, int ld) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int i = ii[q], j = jj[q];
-        const double ci = col[i], rj = rowp[j];
-        const double other = fma(-ci, rj, v[q]);
-        const double on_col = -ci * inv;
-        const double on_row = bsel(j == k, inv, rj);
-        const double nv = bsel(i == k, on_row, bsel(j == k, on_col, other));
-        v[q] = nv;
-        if (valid[q]) M[i * ld + j] = nv;
-    }
-}
-
-template <int Q>
-__device__ inline void gj_load(const double *M, int R, int ld, int t, int nt, double *v, int *ii, int *jj,
-                               bool *valid) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int e = t + q * nt;
-        valid[q] = e < R * R;
-        const int i = valid[q] ? e / R : 0, j = valid[q] ? e - (e / R) * R : 0;
-        ii[q] = i;
-        jj[q] = j;
-        v[q] = M[i * ld + j];
-    }
 }
 
 // Gauss-Jordan elimination of B1 (R <= 16) by the first wavefront alone,
@@ -191,7 +147,7 @@ __device__ inline void gj_load(const double *M, int R, int ld, int t, int nt, do
 // l % 16 of rows l / 16 + 4 q (q < 4), and each step fetches the pivot, the
 // pivot column and the pivot row from the owning lanes by shuffles.
 // Returns 1 if a pivot falls below 1e-12 maxdiag (B1 is then untouched).
-__device__ inline int gj_wave(double *B1, int R, int ld, double maxdiag) {
+__device__ __forceinline__ int gj_wave(double *B1, int R, int ld, double maxdiag) {
     const int l = threadIdx.x, j = l & 15, i0 = l >> 4;
     double v[4];
 #pragma unroll
@@ -224,21 +180,112 @@ __device__ inline int gj_wave(double *B1, int R, int ld, double maxdiag) {
     return 0;
 }
 
+// Blocked Gauss-Jordan elimination of the R x R matrix M (stride ld) with
+// 4 x 4 pivot blocks: the matrix is padded to Rp = 4 ceil(R / 4) with the
+// identity (padding is read, never stored, and stays the identity), thread
+// t < (Rp / 4)^2 owns the 4 x 4 tile (t / (Rp/4), t % (Rp/4)) in registers,
+// and block step kb (K = 4 kb .. 4 kb + 3) does, with P = M(K, K):
+//   M(K, K) <- P^{-1},  M(K, j) <- P^{-1} M(K, j),  M(i, K) <- -M(i, K) P^{-1},
+//   M(i, j) <- M(i, j) - M(i, K) P^{-1} M(K, j)      (i, j not in K),
+// which is four scalar Gauss-Jordan steps at once.  P^{-1} comes from four
+// scalar steps on P in every thread's registers; their pivots are the
+// pivots of scalar elimination, tested against 1e-12 maxdiag.  Returns 1
+// on a failed pivot (M is then partly eliminated; the caller restores it).
+__device__ inline double mpad(const double *M, int R, int ld, int i, int j) {
+    const double x = M[min(i, R - 1) * ld + min(j, R - 1)];  // always a valid address
+    return (i < R && j < R) ? x : (i == j ? 1.0 : 0.0);
+}
+
+__device__ __forceinline__ int gj_block4(double *M, int R, int ld, double maxdiag) {
+    const int tid = threadIdx.x;
+    const int nbk = (R + 3) >> 2;
+    const bool own = tid < nbk * nbk;
+    const int ti = own ? tid / nbk : 0, tj = own ? tid - (tid / nbk) * nbk : 0;
+    double v[4][4];
+    int addr[4][4];  // where each tile entry is stored: padding entries go to the unused column R
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = 4 * ti + a, j = 4 * tj + b;
+            v[a][b] = mpad(M, R, ld, i, j);
+            addr[a][b] = (own && i < R && j < R) ? i * ld + j : min(i, R - 1) * ld + R;
+        }
+    const double thr = 1e-12 * maxdiag;
+    for (int kb = 0; kb < nbk; ++kb) {
+        double P[4][4], Rw[4][4], Cc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                P[a][b] = mpad(M, R, ld, 4 * kb + a, 4 * kb + b);
+                Rw[a][b] = mpad(M, R, ld, 4 * kb + a, 4 * tj + b);  // M(K, cols of the tile)
+                Cc[a][b] = mpad(M, R, ld, 4 * ti + a, 4 * kb + b);  // M(rows of the tile, K)
+            }
+        __syncthreads();  // every read of this step precedes every write
+        // P^{-1} by four in-place scalar steps (identical in every thread)
+        bool bad = false;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            bad = bad || !(P[p][p] > thr);
+            const double inv = 1.0 / P[p][p];
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b != p) P[p][b] *= inv;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                if (a == p) continue;
+                const double f = P[a][p];
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (b != p) P[a][b] = fma(-f, P[p][b], P[a][b]);
+                P[a][p] = -f * inv;
+            }
+            P[p][p] = inv;
+        }
+        if (bad) return 1;  // uniform: every thread has the same P
+        double Rn[4][4];  // P^{-1} M(K, tile cols): the new pivot rows
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                double t = 0.0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) t = fma(P[a][c], Rw[c][b], t);
+                Rn[a][b] = t;
+            }
+        const bool krow = ti == kb, kcol = tj == kb;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                double cpi = 0.0, upd = v[a][b];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    cpi = fma(-Cc[a][c], P[c][b], cpi);  // -(M(i, K) P^{-1})(a, b)
+                    upd = fma(-Cc[a][c], Rn[c][b], upd);
+                }
+                const double r = kcol ? P[a][b] : Rn[a][b];
+                const double o = kcol ? cpi : upd;
+                v[a][b] = krow ? r : o;
+                M[addr[a][b]] = v[a][b];
+            }
+        __syncthreads();
+    }
+    return 0;
+}
+
 // Scratch for spd_inverse: B1, B2, B3 (R x ld doubles each), tmp (>= R
 // doubles), cs (2*33 doubles), pairs (2*33 ints).  On entry B1 = B3 = V;
 // on exit B1 = V^{-1} (or the pseudo-inverse), B3 = V.  Returns 1 when the
-// pseudo-inverse was used.  All threads of the block must call it, and the
-// block must have at least R*R / QMAX threads (R <= 16 uses the first wave
-// only).  Each step copies the pivot row and column of B1 to LDS scratch
-// (B2, tmp), then every thread updates its entries.
-template <int QMAX>
-__device__ inline int spd_inverse(double *B1, double *B2, const double *B3, double *tmp, int R, int ld, double *cs,
+// pseudo-inverse was used.  All threads of the block must call it; the block
+// needs at least ceil(R / 4)^2 threads (256 for R = 64).
+__device__ __forceinline__ int spd_inverse(double *B1, double *B2, const double *B3, double *tmp, int R, int ld, double *cs,
                                   int *pairs) {
     const int tid = threadIdx.x, nt = blockDim.x;
     int bad = 0;
     const double maxdiag = diag_absmax(B1, R, ld, &bad);
     int failed = (bad || !(maxdiag > 0.0)) ? 1 : 0;
-    double *col = tmp, *row = B2;
     if (!failed && R <= 16) {
         __shared__ int s_failed;
         if (tid < kWave) {
@@ -248,26 +295,7 @@ __device__ inline int spd_inverse(double *B1, double *B2, const double *B3, doub
         __syncthreads();
         failed = s_failed;
     } else if (!failed) {
-        // each thread keeps up to QMAX entries; B1 stays current in LDS
-        double v[QMAX];
-        int ii[QMAX], jj[QMAX];
-        bool valid[QMAX];
-        gj_load<QMAX>(B1, R, ld, tid, nt, v, ii, jj, valid);
-        for (int k = 0; k < R; ++k) {
-            const double piv = B1[k * ld + k];
-            if (!(piv > 1e-12 * maxdiag)) {  // same value on every thread: a uniform exit
-                failed = 1;
-                break;
-            }
-            const double inv = 1.0 / piv;
-            if (tid < R) {
-                col[tid] = B1[tid * ld + k];
-                row[tid] = B1[k * ld + tid] * inv;
-            }
-            __syncthreads();
-            gj_update<QMAX>(v, ii, jj, valid, k, inv, col, row, B1, ld);
-            __syncthreads();
-        }
+        failed = gj_block4(B1, R, ld, maxdiag);
     }
     if (!failed) return 0;
     __syncthreads();

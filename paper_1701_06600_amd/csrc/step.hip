@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a, F
         for (int e = tid; e < In; e += kStepThreads) tw[e] = ((const cx<T> *)fp.tw)[e];
     }
     __syncthreads();
-    const int failed = spd_inverse<kMaxRank * kMaxRank / kStepThreads>(B1, B2, B3, tmp, R, ld, cs, pairs);
+    const int failed = spd_inverse(B1, B2, B3, tmp, R, ld, cs, pairs);
     if (tid == 0 && a.info && failed) *a.info = CPRAND_W_PINV;
     const T scale = (T)(1.0 / sqrt((double)In));
     if (a.mix) {
