@@ -38,6 +38,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the mixing pass on the 400^3 workload (average of
+# the three passes), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of
+# bench.py --legs mixonly, scaled by what the same counters read for a 1 GiB
+# device copy (FETCH_SIZE x 2, WRITE_SIZE x 1).  Valid for the kernel as
+# measured; set to None when the mixing kernel changes until re-measured.
+MIX_TRAFFIC_BYTES = (2 * 125158 + 500052 + 2 * (2 * 250105 + 500000)) * 1024 / 3
+# the same 1 GiB copy (read + write) took 423 us: 5.08 TB/s, the practical ceiling seen
+COPY_GBPS = 2 * 1073741824 / 423e-6 / 1e9
 
 
 def main():
@@ -83,6 +91,13 @@ def main():
     Xv = P.View(X, w.dims)
     init = [torch.as_tensor(M, dtype=torch.float32, device=dev) for M in prob.init]
     torch.cuda.synchronize()
+    if "mixonly" in legs:
+        # only the mixing of the tensor, twice (for hardware counters of the mixing passes)
+        for _ in range(2):
+            Xh, signs, nrm = P.cprand_mix(Xv, w.seed)
+        torch.cuda.synchronize()
+        print(json.dumps({"mixonly": True, "dims": list(w.dims)}), flush=True)
+        return
 
     def opts(mix):
         return P.make_opts(R, S, P_hat=w.P_hat, max_iters=w.max_iters, seed=w.seed, tol=w.tol,
@@ -173,9 +188,10 @@ def main():
         "plain_cprand_iters_per_step": r0[-1]["iters"],
         "gather_mttkrp": {"samples": Sg, "ms": g_ms, "useful_GBps": gather_gbs,
                           "frac_of_hbm": gather_gbs / HBM_PEAK_GBS},
-        "roofline": {"kernel": "mix_pass_kernel", "bound": "hbm", "achieved": mix_achieved,
+        "roofline": {"kernel": "mix_pass_pipe", "bound": "hbm", "achieved": mix_achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": mix_achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": MIX_TRAFFIC_BYTES, "algorithmic_bytes": sum(mix_bytes) / 3,
+                     "copy_GBps": COPY_GBPS},
     }
 
     if not args.no_cpu:

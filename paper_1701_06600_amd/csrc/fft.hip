@@ -157,6 +157,140 @@ __global__ __launch_bounds__(NT) void mix_pass_ct(const Tin *X, cx<float> *Xh, i
     }
 }
 
+// Software-pipelined form of the 16-byte passes above for long tensors: a
+// persistent grid (a few workgroups per CU) walks the tiles t = blockIdx.x,
+// blockIdx.x + gridDim.x, ...; the global loads of the next tile are issued
+// into registers before the FFT of the current tile, so HBM traffic overlaps
+// the LDS work.  Same arithmetic and output as mix_pass_ct.
+template <int L, int TC, int NT, bool FIRST>
+__global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *Xh, int64_t J, int64_t K, ModeInfo xi,
+                                                    int m, const int8_t *signs, const cx<float> *twg) {
+    constexpr int LDT = TC + 1;
+    constexpr int NV = FIRST ? L * TC / 4 : L * TC / 2;  // float4 per tile
+    constexpr int PF = (NV + NT - 1) / NT;                // float4 per thread
+    __shared__ cx<float> buf[L * LDT];
+    __shared__ cx<float> tw[L];
+    // tile offsets and signs in three slots: the slot written for the next
+    // tile was last read two iterations ago, before the previous barrier
+    __shared__ int64_t cbase[3][TC];
+    __shared__ float csign[3][TC];
+    __shared__ float lsign[FIRST ? L : 1];
+    const int tid = threadIdx.x;
+    const int64_t ncols = J * K;
+    const int64_t ntiles = ceil_div(ncols, TC);
+    for (int e = tid; e < L; e += NT) tw[e] = twg[e];
+    int moff = 0;
+    if (FIRST) {
+        for (int mm = 0; mm < m; ++mm) moff += (int)xi.dims[mm];
+        for (int e = tid; e < L; e += NT) lsign[e] = (float)signs[moff + e];
+    }
+    // fiber offsets (and FIRST: sign products over the other modes) of tile t
+    auto tile_info = [&](int64_t t, int slot) {
+        for (int c = tid; c < TC; c += NT) {
+            const int64_t q = t * TC + c;
+            if (q >= ncols) {
+                cbase[slot][c] = 0;
+                csign[slot][c] = 0.f;
+                continue;
+            }
+            int64_t j = q % J, k = q / J;
+            cbase[slot][c] = j + J * L * k;
+            if (FIRST) {
+                float sg = 1.0f;
+                int off = 0;
+                for (int mm = 0; mm < xi.order; ++mm) {
+                    if (mm != m) {
+                        int64_t im;
+                        if (mm < m) {
+                            im = j % xi.dims[mm];
+                            j /= xi.dims[mm];
+                        } else {
+                            im = k % xi.dims[mm];
+                            k /= xi.dims[mm];
+                        }
+                        sg *= (float)signs[off + im];
+                    }
+                    off += (int)xi.dims[mm];
+                }
+                csign[slot][c] = sg;
+            }
+        }
+    };
+    auto tile_nc = [&](int64_t t) { return (int)min((int64_t)TC, ncols - t * TC); };
+    float4 r[PF];
+    auto issue_loads = [&](int slot, int nc) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int e = tid + u * NT;
+            r[u] = float4{0.f, 0.f, 0.f, 0.f};
+            if (e < NV) {
+                if (FIRST) {  // fiber fastest: conflict-free LDS writes, 64 contiguous bytes per fiber per wave
+                    const int c = e % TC, l4 = (e / TC) * 4;
+                    if (c < nc) r[u] = *(const float4 *)(X + cbase[slot][c] + l4);
+                } else {
+                    const int l = e / (TC / 2), c = (e - l * (TC / 2)) * 2;
+                    if (c < nc) r[u] = *(const float4 *)(Xh + cbase[slot][c] + J * (int64_t)l);
+                }
+            }
+        }
+    };
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    tile_info(t, 0);
+    __syncthreads();
+    issue_loads(0, tile_nc(t));
+    const float scale = (float)(1.0 / sqrt((double)L));
+    for (int it = 0; t < ntiles; ++it, t += gridDim.x) {
+        const int cur = it % 3, nxt = (it + 1) % 3;
+        const int nc = tile_nc(t);
+        const int64_t tn = t + gridDim.x;
+        if (tn < ntiles) tile_info(tn, nxt);
+        __syncthreads();  // the previous tile's output reads are done; tile_info(tn) is visible
+        // registers (tile t) -> LDS
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int e = tid + u * NT;
+            if (e >= NV) continue;
+            const float4 v = r[u];
+            if (FIRST) {
+                const int c = e % TC, l4 = (e / TC) * 4;
+                const float sc = c < nc ? csign[cur][c] : 0.f;
+                buf[(l4 + 0) * LDT + c] = {v.x * sc * lsign[l4 + 0], 0.f};
+                buf[(l4 + 1) * LDT + c] = {v.y * sc * lsign[l4 + 1], 0.f};
+                buf[(l4 + 2) * LDT + c] = {v.z * sc * lsign[l4 + 2], 0.f};
+                buf[(l4 + 3) * LDT + c] = {v.w * sc * lsign[l4 + 3], 0.f};
+            } else {
+                const int l = e / (TC / 2), c = (e - l * (TC / 2)) * 2;
+                buf[l * LDT + c] = {v.x, v.y};
+                buf[l * LDT + c + 1] = {v.z, v.w};
+            }
+        }
+        // the next tile's loads stay in flight through this tile's FFT
+        if (tn < ntiles) issue_loads(nxt, tile_nc(tn));
+        __syncthreads();
+        fft_ct<float, L, TC, NT, -1>(buf, tw);
+        __syncthreads();
+        if (FIRST) {
+            for (int e = tid; e < L * TC / 2; e += NT) {
+                const int c = e % TC, l2 = (e / TC) * 2;
+                if (c < nc) {
+                    const cx<float> a = buf[l2 * LDT + c], b = buf[(l2 + 1) * LDT + c];
+                    *(float4 *)(Xh + cbase[cur][c] + l2) = {a.re * scale, a.im * scale, b.re * scale, b.im * scale};
+                }
+            }
+        } else {
+            for (int e = tid; e < L * TC / 2; e += NT) {
+                const int l = e / (TC / 2), c = (e - l * (TC / 2)) * 2;
+                if (c < nc) {
+                    const cx<float> a = buf[l * LDT + c], b = buf[l * LDT + c + 1];
+                    *(float4 *)(Xh + cbase[cur][c] + J * (int64_t)l) = {a.re * scale, a.im * scale, b.re * scale,
+                                                                       b.im * scale};
+                }
+            }
+        }
+    }
+}
+
 // Generic tensor pass (any {2,3,5,7}-smooth length, float or double).
 template <typename T, typename Tin>
 __global__ __launch_bounds__(256) void mix_pass_rt(FftPlan fp, const Tin *X, cx<T> *Xh, int64_t J, int64_t K,
@@ -404,24 +538,49 @@ FftPlan *fft_plan_get(int64_t L, bool dbl, hipError_t *err) {
     return heap;
 }
 
+// Compute units of the current device (cached per device).
+static int device_cus() {
+    static std::mutex mu;
+    static std::map<int, int> cus;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cus.find(dev);
+    if (it != cus.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+    cus[dev] = n;
+    return n;
+}
+
 template <int L, int TC, int NT>
 static hipError_t launch_ct_pass(const FftPlan *fp, const ModeInfo &xi, const void *X, int xkind, void *Xhat, int m,
                                  bool first, const int8_t *signs, int64_t J, int64_t K, hipStream_t st) {
     const unsigned nb = (unsigned)ceil_div(J * K, TC);
     const cx<float> *tw = (const cx<float> *)fp->tw;
     const bool xa = (((uintptr_t)X) & 15) == 0, ha = (((uintptr_t)Xhat) & 15) == 0;
+    // persistent grid for the pipelined kernel: as many workgroups as fit per
+    // CU by LDS (at most 8), one pass over the CUs
+    constexpr size_t kLds = (size_t)L * (TC + 1) * 8 + (size_t)L * 8 + TC * 36 + L * 4;
+    const unsigned per_cu = (unsigned)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / kLds));
+    const unsigned np = (unsigned)std::min<int64_t>((int64_t)nb, (int64_t)device_cus() * per_cu);
     if (first) {
         if (xkind != K_F32) return hipErrorInvalidValue;
-        if (L % 4 == 0 && J == 1 && xa && ha)
-            hipLaunchKernelGGL((mix_pass_ct<float, L, TC, NT, true, (L % 4 == 0)>), dim3(nb), dim3(NT), 0, st,
-                               (const float *)X, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
-        else
+        if constexpr (L % 4 == 0) {
+            if (J == 1 && xa && ha) {
+                hipLaunchKernelGGL((mix_pass_pipe<L, TC, NT, true>), dim3(np), dim3(NT), 0, st, (const float *)X,
+                                   (cx<float> *)Xhat, J, K, xi, m, signs, tw);
+                return hipGetLastError();
+            }
+        }
+        {
             hipLaunchKernelGGL((mix_pass_ct<float, L, TC, NT, true, false>), dim3(nb), dim3(NT), 0, st,
                                (const float *)X, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
+        }
     } else {
         if (J > 1 && J % TC == 0 && ha)
-            hipLaunchKernelGGL((mix_pass_ct<float, L, TC, NT, false, true>), dim3(nb), dim3(NT), 0, st,
-                               (const float *)nullptr, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
+            hipLaunchKernelGGL((mix_pass_pipe<L, TC, NT, false>), dim3(np), dim3(NT), 0, st, (const float *)nullptr,
+                               (cx<float> *)Xhat, J, K, xi, m, signs, tw);
         else
             hipLaunchKernelGGL((mix_pass_ct<float, L, TC, NT, false, false>), dim3(nb), dim3(NT), 0, st,
                                (const float *)nullptr, (cx<float> *)Xhat, J, K, xi, m, signs, tw);

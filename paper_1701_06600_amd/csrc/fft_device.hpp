@@ -43,7 +43,7 @@ struct FftPlan {
 
 // r-point DFT in place, sign DIR (-1 forward, +1 inverse).
 template <typename T, int R, int DIR>
-__device__ inline void small_dft(cx<T> *v, const cx<T> *tw, int L) {
+__device__ __forceinline__ void small_dft(cx<T> *v, const cx<T> *tw, int L) {
     if constexpr (R == 2) {
         cx<T> a = v[0], b = v[1];
         v[0] = cadd(a, b);
@@ -117,7 +117,7 @@ __device__ inline int divmod_small(int a, int b, float binv, int &r) {
 }
 
 template <typename T, int R, int DIR>
-__device__ inline void stage_rt(const cx<T> *in, cx<T> *out, int L, int ldt, int tc, int Ns, const cx<T> *tw) {
+__device__ __forceinline__ void stage_rt(const cx<T> *in, cx<T> *out, int L, int ldt, int tc, int Ns, const cx<T> *tw) {
     const int nb = (L / R) * tc;
     const int twstep = L / (Ns * R);
     const int LR = L / R;
@@ -158,7 +158,7 @@ __device__ inline void stage_rt(const cx<T> *in, cx<T> *out, int L, int ldt, int
 }
 
 template <typename T, int DIR>
-__device__ cx<T> *fft_tile_rt(cx<T> *buf0, cx<T> *buf1, const FftPlan &fp, int ldt, int tc, const cx<T> *tw) {
+__device__ __forceinline__ cx<T> *fft_tile_rt(cx<T> *buf0, cx<T> *buf1, const FftPlan &fp, int ldt, int tc, const cx<T> *tw) {
     cx<T> *in = buf0, *out = buf1;
     int Ns = 1;
     const int L = (int)fp.L;
@@ -202,7 +202,7 @@ constexpr RadixList factor_len(int L) {
 }
 
 template <typename T, int L, int TC, int NT, int DIR, int S = 0, int NS = 1>
-__device__ inline void fft_ct(cx<T> *buf, const cx<T> *tw) {
+__device__ __forceinline__ void fft_ct(cx<T> *buf, const cx<T> *tw) {
     constexpr RadixList RL = factor_len(L);
     if constexpr (S < RL.n) {
         constexpr int R = RL.r[S];
