@@ -48,6 +48,7 @@ struct Geo {
 };
 
 constexpr int kUnroll = 8;  // k-steps (of 4 samples) whose fiber loads are in flight together
+constexpr int kWholeFiberS = 4096;  // sample sets from this size on use whole-fiber workgroups
 
 // LDS row stride (in T) for the B operand: >= 16*CT and, for float, an odd
 // multiple of 16 words so that two B rows read by one half-wave hit
@@ -182,13 +183,17 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
         }
     }
 
-    // ---- (4) fibers x Z_S on MFMA
+    // ---- (4) fibers x Z_S on MFMA, one row group of G::RPW rows per wave at a
+    // time (a workgroup covers rows_wg rows: one group per wave for short
+    // sample chunks, whole fibers for long ones)
     const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
-    const int rowbase = blockIdx.x * a.rows_wg + wv * G::RPW;
-    if (rowbase >= a.In) return;
     const int In = a.In;
+    const int row_end = min(In, (int)(blockIdx.x + 1) * a.rows_wg);
     const T *xp = (const T *)a.X;
     const int64_t sn = a.mi.strides[n];
+    T *wp = (T *)a.wpart + (size_t)chunk * a.ncols * In;
+    for (int rowbase = blockIdx.x * a.rows_wg + wv * G::RPW; rowbase < row_end;
+         rowbase += (int)(blockDim.x >> 6) * G::RPW) {
     const int row0 = rowbase + G::VE * li;
 
     Acc acc[CT][G::VE];
@@ -260,7 +265,6 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
     // Output tile row i' of MFMA c is fiber row rowbase + VE*i' + c.  Lane l
     // holds column 16*ct + l%16 and tile rows i' = 4*(l/16) + v (FP32
     // 16x16x4) or i' = l/16 + 4*v (FP64 16x16x4), v = 0..3.
-    T *wp = (T *)a.wpart + (size_t)chunk * a.ncols * In;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
         const int col = ct * 16 + li;
@@ -272,9 +276,10 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
             for (int c = 0; c < G::VE; ++c) {
                 const int ip = sizeof(T) == 8 ? lk + 4 * vv : 4 * lk + vv;
                 const int row = rowbase + G::VE * ip + c;
-                if (row < In) dst[row] = acc[ct][c][vv];
+                if (row < row_end) dst[row] = acc[ct][c][vv];
             }
     }
+    }  // row groups
 }
 
 // ---------------------------------------------------------------------------
@@ -305,7 +310,14 @@ GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_o
         return head + (size_t)k * ldb * tsize * 2;  // room for Bre + (Bim or Zraw)
     };
     int kc = 64;
-    if (max_chunks > 0) {
+    if (max_chunks == 0 && S >= kWholeFiberS) {
+        // long sample sets: every workgroup reads whole fibers (all row groups)
+        // of its chunk, about a thousand chunks
+        g.row_blocks = 1;
+        g.rows_wg = (int)(ceil_div(In, (int64_t)g.waves * rpw) * g.waves * rpw);
+        kc = (int)std::min<int64_t>(128, std::max<int64_t>(16, ceil_div(ceil_div(S, 1024), 16) * 16));
+        while (kc > 16 && lds_for(kc) > 65536) kc -= 16;
+    } else if (max_chunks > 0) {
         kc = (int)ceil_div(ceil_div(S, max_chunks), 16) * 16;
         while (kc > 16 && lds_for(kc) > 150 * 1024) kc -= 16;
     } else {
@@ -387,80 +399,140 @@ hipError_t launch_gather(const GatherPlan &gp, const GatherArgs &a, hipStream_t 
 }
 
 // ---------------------------------------------------------------------------
+// Partial-product reductions.  Every sum runs in partial order; when there
+// are many partials, groups of kGroup consecutive partials are first summed
+// in place (group g written over its first partial, in parallel over groups
+// and elements), and the group sums are then added in group order.
+
+constexpr int kGroup = 32;
+
+template <typename T>
+__global__ __launch_bounds__(256) void group_sum_kernel(T *parts, int32_t np, int64_t count) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const int p0 = blockIdx.y * kGroup, p1 = min(np, p0 + kGroup);
+    double acc = 0.0;
+    int p = p0;
+    for (; p + 8 <= p1; p += 8) {
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = parts[(size_t)(p + k) * count + e];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += (double)v[k];
+    }
+    for (; p < p1; ++p) acc += (double)parts[(size_t)p * count + e];
+    parts[(size_t)p0 * count + e] = (T)acc;
+}
+
+// Sums groups of partials in place when np > kGroup; on return the partials
+// to add are parts[p * pstride] for p < np.
+static hipError_t group_presum(void *parts, bool dbl, int32_t &np, int64_t count, int64_t &pstride,
+                               hipStream_t st) {
+    pstride = count;
+    if (np <= kGroup) return hipSuccess;
+    const int ng = (int)ceil_div(np, kGroup);
+    dim3 grid((unsigned)ceil_div(count, 256), (unsigned)ng);
+    if (dbl)
+        hipLaunchKernelGGL(group_sum_kernel<double>, grid, dim3(256), 0, st, (double *)parts, np, count);
+    else
+        hipLaunchKernelGGL(group_sum_kernel<float>, grid, dim3(256), 0, st, (float *)parts, np, count);
+    np = ng;
+    pstride = count * kGroup;
+    return hipGetLastError();
+}
+
 // Reduce partials into row-major W and V (real kinds).
 template <typename T>
-__global__ __launch_bounds__(256) void reduce_wv_kernel(const T *wpart, const double *vpart,
-                                                        int32_t chunks, int32_t In, int32_t R,
-                                                        T *W, double *V) {
+__global__ __launch_bounds__(256) void reduce_wv_kernel(const T *wpart, int64_t wstride, const double *vpart,
+                                                        int64_t vstride, int32_t wchunks, int32_t vchunks,
+                                                        int32_t In, int32_t R, T *W, double *V) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nw = (int64_t)In * R;
     if (e < nw) {
         if (!W) return;
         const int64_t i = e / R, r = e - i * R;
         double acc = 0.0;
-        for (int c = 0; c < chunks; ++c) acc += (double)wpart[((size_t)c * R + r) * In + i];
+        for (int c = 0; c < wchunks; ++c) acc += (double)wpart[(size_t)c * wstride + r * In + i];
         W[e] = (T)acc;
     } else if (e < nw + (int64_t)R * R) {
         const int64_t p = e - nw;
         double acc = 0.0;
-        for (int c = 0; c < chunks; ++c) acc += vpart[(size_t)c * R * R + p];
+        for (int c = 0; c < vchunks; ++c) acc += vpart[(size_t)c * vstride + p];
         V[p] = acc;
     }
 }
 
-// out[e] = sum over p of parts[p * count + e], in order.
+// out[e] = sum over p of parts[p * pstride + e], in order.
 template <typename T>
-__global__ __launch_bounds__(256) void sum_parts_kernel(const T *parts, int32_t np, int64_t count, T *out) {
+__global__ __launch_bounds__(256) void sum_parts_kernel(const T *parts, int32_t np, int64_t count, int64_t pstride,
+                                                        T *out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
     double acc = 0.0;
-    for (int p = 0; p < np; ++p) acc += (double)parts[(size_t)p * count + e];
+    for (int p = 0; p < np; ++p) acc += (double)parts[(size_t)p * pstride + e];
     out[e] = (T)acc;
 }
 
-// out[e] (FP64) = sum over p of parts[p * count + e], in order.
+// out[e] (FP64) = sum over p of parts[p * pstride + e], in order.
 template <typename T>
-__global__ __launch_bounds__(256) void sum_parts_f64_kernel(const T *parts, int32_t np, int64_t count, double *out) {
+__global__ __launch_bounds__(256) void sum_parts_f64_kernel(const T *parts, int32_t np, int64_t count,
+                                                            int64_t pstride, double *out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
     double acc = 0.0;
-    for (int p = 0; p < np; ++p) acc += (double)parts[(size_t)p * count + e];
+    for (int p = 0; p < np; ++p) acc += (double)parts[(size_t)p * pstride + e];
     out[e] = acc;
 }
 
 hipError_t launch_sum_parts_f64(const void *parts, int32_t np, int64_t count, bool in_double, double *out,
                                 hipStream_t st) {
+    int64_t ps = count;
+    hipError_t e = group_presum(const_cast<void *>(parts), in_double, np, count, ps, st);
+    if (e != hipSuccess) return e;
     const int nb = (int)ceil_div(count, 256);
     if (in_double)
         hipLaunchKernelGGL(sum_parts_f64_kernel<double>, dim3(nb), dim3(256), 0, st, (const double *)parts, np, count,
-                           out);
+                           ps, out);
     else
         hipLaunchKernelGGL(sum_parts_f64_kernel<float>, dim3(nb), dim3(256), 0, st, (const float *)parts, np, count,
-                           out);
+                           ps, out);
     return hipGetLastError();
 }
 
 hipError_t launch_sum_parts(const void *parts, int32_t np, int64_t count, bool dbl, void *out, hipStream_t st) {
+    int64_t ps = count;
+    hipError_t e = group_presum(const_cast<void *>(parts), dbl, np, count, ps, st);
+    if (e != hipSuccess) return e;
     const int nb = (int)ceil_div(count, 256);
     if (dbl)
-        hipLaunchKernelGGL(sum_parts_kernel<double>, dim3(nb), dim3(256), 0, st, (const double *)parts, np, count,
+        hipLaunchKernelGGL(sum_parts_kernel<double>, dim3(nb), dim3(256), 0, st, (const double *)parts, np, count, ps,
                            (double *)out);
     else
-        hipLaunchKernelGGL(sum_parts_kernel<float>, dim3(nb), dim3(256), 0, st, (const float *)parts, np, count,
+        hipLaunchKernelGGL(sum_parts_kernel<float>, dim3(nb), dim3(256), 0, st, (const float *)parts, np, count, ps,
                            (float *)out);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_wv(const GatherPlan &gp, const void *wpart, const double *vpart,
                             void *W, double *V, hipStream_t st) {
+    const bool dbl = gp.kind == K_F64 || gp.kind == K_C128;
+    int32_t wc = gp.chunks, vc = gp.chunks;
+    int64_t ws = (int64_t)gp.ncols * gp.In, vs = (int64_t)gp.R * gp.R;
+    hipError_t e = hipSuccess;
+    if (W && wpart) {
+        // the chunk partials are [chunk][ncols][In]; presum over whole chunk slabs
+        e = group_presum(const_cast<void *>(wpart), dbl, wc, ws, ws, st);
+    }
+    if (e == hipSuccess) e = group_presum(const_cast<double *>(vpart), true, vc, vs, vs, st);
+    if (e != hipSuccess) return e;
     const int64_t tot = (int64_t)gp.In * gp.R + (int64_t)gp.R * gp.R;
     const int nb = (int)ceil_div(tot, 256);
-    if (gp.kind == K_F64 || gp.kind == K_C128)
-        hipLaunchKernelGGL(reduce_wv_kernel<double>, dim3(nb), dim3(256), 0, st,
-                           (const double *)wpart, vpart, gp.chunks, gp.In, gp.R, (double *)W, V);
+    if (dbl)
+        hipLaunchKernelGGL(reduce_wv_kernel<double>, dim3(nb), dim3(256), 0, st, (const double *)wpart, ws, vpart, vs,
+                           wc, vc, gp.In, gp.R, (double *)W, V);
     else
-        hipLaunchKernelGGL(reduce_wv_kernel<float>, dim3(nb), dim3(256), 0, st,
-                           (const float *)wpart, vpart, gp.chunks, gp.In, gp.R, (float *)W, V);
+        hipLaunchKernelGGL(reduce_wv_kernel<float>, dim3(nb), dim3(256), 0, st, (const float *)wpart, ws, vpart, vs,
+                           wc, vc, gp.In, gp.R, (float *)W, V);
     return hipGetLastError();
 }
 
