@@ -89,20 +89,29 @@ struct CdfPtrs {
     const uint64_t *p[kMaxOrder];
 };
 
+// Word j (0..3) of a Philox block, by selects (a runtime index into the
+// block would put it in scratch memory).
+__device__ inline uint64_t u64x4_get(const u64x4 &b, int j) {
+    return j == 0 ? b.v[0] : j == 1 ? b.v[1] : j == 2 ? b.v[2] : b.v[3];
+}
+
 // Draw the multi-index of sample s (modes != n) and its importance weight.
-// idx_out[m] receives the row of mode m (undefined for m == n).
+// idx_out[m] receives the row of mode m (undefined for m == n).  The mode
+// loop is unrolled to kMaxOrder so that idx_out stays in registers.
 __device__ inline double draw_sample(const ModeInfo &mi, uint64_t seed, uint64_t t, int64_t s,
-                                     const CdfPtrs *cdf, int64_t *idx_out) {
+                                     const CdfPtrs &cdf, bool use_cdf, int64_t *idx_out) {
     double w = 1.0;
     int k = 0;
     u64x4 blk;
-    for (int m = 0; m < mi.order; ++m) {
+#pragma unroll
+    for (int m = 0; m < kMaxOrder; ++m) {
+        if (m >= mi.order) break;
         if (m == mi.n) continue;
         if ((k & 3) == 0) blk = philox4x64_10((uint64_t)s, t, (uint64_t)mi.n, (uint64_t)(k >> 2), seed, kTagSamples);
-        uint64_t u = blk.v[k & 3];
+        const uint64_t u = u64x4_get(blk, k & 3);
         const int64_t I = mi.dims[m];
-        if (cdf) {
-            const uint64_t *c = cdf->p[m];
+        if (use_cdf) {
+            const uint64_t *c = cdf.p[m];
             const uint64_t Q = c[I];
             const int64_t i = cdf_search(c, I, mulhi64(u, Q));
             idx_out[m] = i;

@@ -564,9 +564,19 @@ static hipError_t launch_ct_pass(const FftPlan *fp, const ModeInfo &xi, const vo
     constexpr size_t kLds = (size_t)L * (TC + 1) * 8 + (size_t)L * 8 + TC * 36 + L * 4;
     const unsigned per_cu = (unsigned)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / kLds));
     const unsigned np = (unsigned)std::min<int64_t>((int64_t)nb, (int64_t)device_cus() * per_cu);
+    // the pipelined kernel holds the next tile in registers: long fibers
+    // (more than 8 vectors per thread) would spill, they use mix_pass_ct
+    constexpr bool kPipe = (L * TC / 2 + NT - 1) / NT <= 8;
     if (first) {
         if (xkind != K_F32) return hipErrorInvalidValue;
         if constexpr (L % 4 == 0) {
+            if (J == 1 && xa && ha && !kPipe) {
+                hipLaunchKernelGGL((mix_pass_ct<float, L, TC, NT, true, true>), dim3(nb), dim3(NT), 0, st,
+                                   (const float *)X, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
+                return hipGetLastError();
+            }
+        }
+        if constexpr (L % 4 == 0 && kPipe) {
             if (J == 1 && xa && ha) {
                 hipLaunchKernelGGL((mix_pass_pipe<L, TC, NT, true>), dim3(np), dim3(NT), 0, st, (const float *)X,
                                    (cx<float> *)Xhat, J, K, xi, m, signs, tw);
@@ -578,9 +588,16 @@ static hipError_t launch_ct_pass(const FftPlan *fp, const ModeInfo &xi, const vo
                                (const float *)X, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
         }
     } else {
+        if constexpr (kPipe) {
+            if (J > 1 && J % TC == 0 && ha) {
+                hipLaunchKernelGGL((mix_pass_pipe<L, TC, NT, false>), dim3(np), dim3(NT), 0, st,
+                                   (const float *)nullptr, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
+                return hipGetLastError();
+            }
+        }
         if (J > 1 && J % TC == 0 && ha)
-            hipLaunchKernelGGL((mix_pass_pipe<L, TC, NT, false>), dim3(np), dim3(NT), 0, st, (const float *)nullptr,
-                               (cx<float> *)Xhat, J, K, xi, m, signs, tw);
+            hipLaunchKernelGGL((mix_pass_ct<float, L, TC, NT, false, true>), dim3(nb), dim3(NT), 0, st,
+                               (const float *)nullptr, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
         else
             hipLaunchKernelGGL((mix_pass_ct<float, L, TC, NT, false, false>), dim3(nb), dim3(NT), 0, st,
                                (const float *)nullptr, (cx<float> *)Xhat, J, K, xi, m, signs, tw);

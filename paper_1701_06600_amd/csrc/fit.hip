@@ -7,6 +7,8 @@
 // block sums, and a one-block final kernel.
 #include <math.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace cprand {
@@ -35,9 +37,11 @@ __device__ inline void fit_entry(const FitArgs &a, int64_t p, int64_t *row, doub
     const int N = a.mi.order;
     u64x4 blk;
     int64_t off = 0;
-    for (int k = 0; k < N; ++k) {
+#pragma unroll
+    for (int k = 0; k < kMaxOrder; ++k) {
+        if (k >= N) break;
         if ((k & 3) == 0) blk = philox4x64_10((uint64_t)p, 0, 0, (uint64_t)(k >> 2), a.seed, kTagFit);
-        row[k] = (int64_t)mulhi64(blk.v[k & 3], (uint64_t)a.mi.dims[k]);
+        row[k] = (int64_t)mulhi64(u64x4_get(blk, k & 3), (uint64_t)a.mi.dims[k]);
         off += row[k] * a.mi.strides[k];
     }
     load_elem(a.X, a.kind, off, xr, xi);
@@ -224,8 +228,63 @@ __global__ __launch_bounds__(256) void normsq_kernel(ModeInfo mi, const void *X,
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Contiguous, 16-byte aligned data of real or complex FP32 / FP64: the sum of
+// squares of all scalar components.  Block b covers a fixed range of 16-byte
+// vectors (four loads in flight per thread); block 0 also adds the scalar
+// tail past the last whole vector.
+template <typename T>
+__global__ __launch_bounds__(256) void normsq_vec_kernel(const T *x, int64_t ncomp, double *part) {
+    __shared__ double sh[256 / kWave];
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
+    constexpr int VL = 16 / sizeof(T);
+    const int64_t nvec = ncomp / VL;
+    const int64_t per = ceil_div(nvec, (int64_t)gridDim.x);
+    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(nvec, b0 + per);
+    const V *v = (const V *)x;
+    double acc = 0.0;
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += 4 * (int64_t)blockDim.x) {
+        V q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = e + u * (int64_t)blockDim.x;
+            q[u] = k < b1 ? v[k] : V{};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const T *c = (const T *)&q[u];
+#pragma unroll
+            for (int j = 0; j < VL; ++j) acc += (double)c[j] * (double)c[j];
+        }
+    }
+    if (blockIdx.x == 0)
+        for (int64_t e = nvec * VL + threadIdx.x; e < ncomp; e += blockDim.x) acc += (double)x[e] * (double)x[e];
+    const double s = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 hipError_t launch_normsq_partial(const ModeInfo &mi, const void *X, int kind, double *part,
                                  int32_t *nparts, hipStream_t st) {
+    {
+        int64_t P = 1, expect = 1;
+        bool contiguous = true;
+        for (int m = 0; m < mi.order; ++m) {
+            if (mi.strides[m] != expect) contiguous = false;
+            expect *= mi.dims[m];
+            P *= mi.dims[m];
+        }
+        if (contiguous && (((uintptr_t)X) & 15) == 0 && kind != K_BF16) {
+            const bool cplx = kind == K_C64 || kind == K_C128;
+            const int64_t ncomp = P * (cplx ? 2 : 1);
+            *nparts = kNormBlocks;
+            if (kind == K_F32 || kind == K_C64)
+                hipLaunchKernelGGL(normsq_vec_kernel<float>, dim3(kNormBlocks), dim3(256), 0, st, (const float *)X,
+                                   ncomp, part);
+            else
+                hipLaunchKernelGGL(normsq_vec_kernel<double>, dim3(kNormBlocks), dim3(256), 0, st, (const double *)X,
+                                   ncomp, part);
+            return hipGetLastError();
+        }
+    }
     int64_t P = 1, expect = 1;
     bool contiguous = true;
     for (int m = 0; m < mi.order; ++m) {

@@ -102,21 +102,28 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
         int64_t row[kMaxOrder];
         double wv = 1.0;
         int64_t base = 0;
+        // mode loops unrolled to kMaxOrder: row[] stays in registers
         if (sl < ns) {
             const int64_t s = s0 + sl;
             if (a.idx) {
-                for (int m = 0; m < N; ++m) row[m] = (m == n) ? 0 : a.idx[s * N + m];
+#pragma unroll
+                for (int m = 0; m < kMaxOrder; ++m)
+                    if (m < N) row[m] = (m == n) ? 0 : a.idx[s * N + m];
                 if (a.w) wv = a.w[s];
             } else {
-                wv = draw_sample(a.mi, a.seed, tt, s, a.use_cdf ? &a.cdf : nullptr, row);
+                wv = draw_sample(a.mi, a.seed, tt, s, a.cdf, a.use_cdf != 0, row);
             }
-            for (int m = 0; m < N; ++m)
-                if (m != n) base += row[m] * a.mi.strides[m];
+#pragma unroll
+            for (int m = 0; m < kMaxOrder; ++m)
+                if (m < N && m != n) base += row[m] * a.mi.strides[m];
         } else {
-            for (int m = 0; m < N; ++m) row[m] = 0;
+#pragma unroll
+            for (int m = 0; m < kMaxOrder; ++m) row[m] = 0;
             wv = 0.0;
         }
-        for (int m = 0; m < N; ++m) s_idx[sl * N + m] = (int32_t)row[m];
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m)
+            if (m < N) s_idx[sl * N + m] = (m == n) ? 0 : (int32_t)row[m];
         s_base[sl] = base;
         s_w[sl] = wv;
     }

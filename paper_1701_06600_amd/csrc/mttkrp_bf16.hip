@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void gather_contract_bf16(BfArgs a) {
                 for (int m = 0; m < N; ++m) row[m] = (m == n) ? 0 : a.idx[s * N + m];
                 if (a.w) wv = a.w[s];
             } else {
-                wv = draw_sample(a.mi, a.seed, tt, s, a.use_cdf ? &a.cdf : nullptr, row);
+                wv = draw_sample(a.mi, a.seed, tt, s, a.cdf, a.use_cdf != 0, row);
             }
             for (int m = 0; m < N; ++m)
                 if (m != n) base += row[m] * a.mi.strides[m];

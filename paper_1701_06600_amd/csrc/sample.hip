@@ -12,8 +12,10 @@ __global__ __launch_bounds__(256) void sample_kernel(ModeInfo mi, int32_t S, uin
     if (s >= S) return;
     const uint64_t tt = t_dev ? *t_dev : t;
     int64_t row[kMaxOrder];
-    const double ws = draw_sample(mi, seed, tt, s, use_cdf ? &cdf : nullptr, row);
-    for (int m = 0; m < mi.order; ++m) idx[s * mi.order + m] = (m == mi.n) ? -1 : (int32_t)row[m];
+    const double ws = draw_sample(mi, seed, tt, s, cdf, use_cdf != 0, row);
+#pragma unroll
+    for (int m = 0; m < kMaxOrder; ++m)
+        if (m < mi.order) idx[s * mi.order + m] = (m == mi.n) ? -1 : (int32_t)row[m];
     if (w) w[s] = ws;
 }
 
