@@ -148,7 +148,7 @@ def cprand_fit_est(X, normX, A, lam, R, P_hat, seed, fit_out=None, ws=None):
     if fit_out is None:
         fit_out = torch.empty(1, dtype=torch.float64, device=X.data.device)
     if ws is None:
-        ws = torch.empty(max(256, math.ceil(P_hat / 256) * 8), dtype=torch.uint8, device=X.data.device)
+        ws = workspace(X, R, 1, P_hat)
     arr = _ptr_array(A, order)
     _check(_lib.cprand_fit_est(C.byref(X.c()), _ptr(normX), arr, _ptr(lam), R, P_hat, C.c_uint64(seed),
                                _ptr(fit_out), _ptr(ws), ws.numel(), _stream()))

@@ -211,7 +211,7 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         const void *vd = view_ptr(p, v, xdata);
         const int64_t In = p->dims[n];
         // the whole post-gather step in one workgroup when it fits in LDS
-        bool fused = step_finish_lds((int32_t)In, R, p->mix, p->dbl) <= 156 * 1024;
+        bool fused = step_finish_lds((int32_t)In, R, p->mix) <= 156 * 1024;
         const bool rcontig = p->refine && (p->rview[n].data ? true : contig_x[n]);
         GatherPlan gp = plan_gather(p->gkind, R, p->o.S, In, v.data ? true : contig_x[n],
                                     fused ? kChunksFused : kChunksSplit);
@@ -299,9 +299,7 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
             sa.Ahat = p->mix ? p->fhat[n] : nullptr;
             sa.lambda = p->lambda;
             sa.info = p->info;
-            FftPlan *fp = nullptr;
-            if (p->mix) fp = fft_plan_get(In, p->dbl, &e);
-            if (e == hipSuccess) e = launch_step_finish(sa, fp, p->dbl, st);
+            e = launch_step_finish(sa, p->dbl, st);
             continue;
         }
         // the split path: partial products summed by coalesced FP64 kernels first
@@ -365,23 +363,20 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
     FitArgs fa = fit_args(p, xdata);
     fa.frow = p->frow;
     fa.fx = p->fx;
+    if (!p->adaptive) {
+        const size_t tsz = p->dbl ? 8 : 4;
+        for (int m = 0; m < N; ++m) {  // under mixing the state is A-hat (A is formed at the end)
+            fa.snap.src[m] = p->mix ? p->fhat[m] : p->fac[m];
+            fa.snap.words[m] = (int64_t)(p->dims[m] * R * tsz * (p->mix ? 2 : 1) / 4);
+        }
+        fa.snap.nsrc = N;
+        fa.snap.lambda = p->lambda;
+        fa.snap.R = R;
+        fa.snap.dst0 = p->snapbuf[0];
+        fa.snap.dst1 = p->snapbuf[1];
+    }
     int32_t nb = 0;
     e = launch_fit_partial(fa, &nb, st);
-    if (e == hipSuccess && !p->adaptive) {
-        SnapArgs sa{};
-        const size_t tsz = p->dbl ? 8 : 4;
-        for (int m = 0; m < N; ++m) {
-            sa.src[m] = p->fac[m];
-            sa.words[m] = (int64_t)(p->dims[m] * R * tsz / 4);
-        }
-        sa.nsrc = N;
-        sa.lambda = p->lambda;
-        sa.R = R;
-        sa.dst0 = p->snapbuf[0];
-        sa.dst1 = p->snapbuf[1];
-        sa.t_dev = p->t_dev;
-        e = launch_snapshot(sa, st);
-    }
     return e;
 }
 
@@ -540,7 +535,7 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     if (e == hipSuccess && p->refine) e = dalloc(p, &p->rpart, rpart);
     if (e == hipSuccess && p->refine) e = dalloc(p, (void **)&p->vrpart, vpart * 2 + 256);
     if (e == hipSuccess) e = dalloc(p, (void **)&p->colsq, (size_t)ceil_div(maxdim, 32) * R * 8);
-    if (e == hipSuccess) e = dalloc(p, (void **)&p->fitpart, (size_t)ceil_div(o.P_hat, 256) * 8);
+    if (e == hipSuccess) e = dalloc(p, (void **)&p->fitpart, (size_t)fit_partials(o.P_hat) * 8);
     if (e == hipSuccess) e = dalloc(p, (void **)&p->normpart, 4096 * 8);
     if (e == hipSuccess) e = dalloc(p, (void **)&p->normX, 8);
     if (e == hipSuccess) e = dalloc(p, (void **)&p->hist_dev, (size_t)o.max_iters * 8);
@@ -549,7 +544,7 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     if (e == hipSuccess) e = dalloc(p, (void **)&p->frow, (size_t)o.P_hat * N * 4);
     if (e == hipSuccess) {
         p->snapbytes = (size_t)R * 8;
-        for (int m = 0; m < N; ++m) p->snapbytes += (size_t)p->dims[m] * R * tsz;
+        for (int m = 0; m < N; ++m) p->snapbytes += (size_t)p->dims[m] * R * tsz * (p->mix ? 2 : 1);
         e = dalloc(p, &p->snapbuf[0], p->snapbytes);
         if (e == hipSuccess) e = dalloc(p, &p->snapbuf[1], p->snapbytes);
     }
@@ -791,8 +786,8 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
             const size_t tsz = p->dbl ? 8 : 4;
             size_t off = 0;
             for (int m = 0; m < N && e == hipSuccess; ++m) {
-                const size_t b = (size_t)p->dims[m] * R * tsz;
-                e = hipMemcpyAsync(p->fac[m], sb + off, b, hipMemcpyDeviceToDevice, st);
+                const size_t b = (size_t)p->dims[m] * R * tsz * (p->mix ? 2 : 1);
+                e = hipMemcpyAsync(p->mix ? p->fhat[m] : p->fac[m], sb + off, b, hipMemcpyDeviceToDevice, st);
                 off += b;
             }
             if (e == hipSuccess) e = hipMemcpyAsync(p->lambda, sb + off, (size_t)R * 8, hipMemcpyDeviceToDevice, st);
@@ -856,6 +851,13 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
     if (graph) (void)hipGraphDestroy(graph);
     if (e != hipSuccess && isfinite(F)) return hip_fail(e, "ALS loop");
     if (!isfinite(F)) return set_error(CPRAND_ENAN, "non-finite fit estimate at iteration %d", it);
+    // under mixing the loop keeps only A-hat: A = D_n F_n^* A-hat (Alg. 4, final unmix)
+    for (int m = 0; p->mix && m < N && e == hipSuccess; ++m) {
+        FftPlan *fp = fft_plan_get(p->dims[m], p->dbl, &e);
+        if (fp) e = launch_factor_mix(fp, p->dbl, (int32_t)p->dims[m], R, p->fhat[m], p->signs + p->seg_off[m],
+                                      p->fac[m], true, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "final unmix");
     hipEventRecord(p->ev[3], st);
     for (int m = 0; m < N && e == hipSuccess; ++m)
         e = hipMemcpyAsync(A_inout[m], p->fac[m], (size_t)p->dims[m] * R * tsz, hipMemcpyDeviceToDevice, st);

@@ -117,7 +117,7 @@ WsLayout ws_layout(const cprand_tensor *X, int32_t R, int32_t S, int32_t P_hat) 
     int64_t maxdim = 1;
     for (int n = 0; n < X->order; ++n) maxdim = std::max(maxdim, X->dims[n]);
     const size_t colsq = (size_t)ceil_div(maxdim, 32) * R * 8;
-    const size_t fit = (size_t)ceil_div(std::max(P_hat, 1), 256) * 8;
+    const size_t fit = (size_t)fit_partials(P_hat) * 8;
     const size_t norm = (size_t)4096 * 8;
     const size_t wtmp = (size_t)maxdim * R * 16;
     w.wpart = 0;
@@ -293,7 +293,7 @@ int cprand_fit_est(const cprand_tensor *X, const double *normX, const void *cons
     if (!normX || !A || !lambda || !fit_out) return set_error(CPRAND_EINVAL, "NULL pointer argument");
     for (int m = 0; m < X->order; ++m)
         if (!A[m]) return set_error(CPRAND_EINVAL, "A[%d] is NULL", m);
-    const size_t need = (size_t)ceil_div(P_hat, 256) * 8;
+    const size_t need = (size_t)fit_partials(P_hat) * 8;
     if (!workspace || workspace_bytes < need) return set_error(CPRAND_EINVAL, "workspace of %zu bytes needed", need);
     const int kind = kind_of(X->dtype);
     FitArgs fa{};

@@ -224,8 +224,8 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
             const int e = tid + u * NT;
             r[u] = float4{0.f, 0.f, 0.f, 0.f};
             if (e < NV) {
-                if (FIRST) {  // fiber fastest: conflict-free LDS writes, 64 contiguous bytes per fiber per wave
-                    const int c = e % TC, l4 = (e / TC) * 4;
+                if (FIRST) {  // the tile's fibers are adjacent (J = 1): one contiguous run of L * TC floats
+                    const int c = e / (L / 4), l4 = (e - c * (L / 4)) * 4;
                     if (c < nc) r[u] = *(const float4 *)(X + cbase[slot][c] + l4);
                 } else {
                     const int l = e / (TC / 2), c = (e - l * (TC / 2)) * 2;
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
             if (e >= NV) continue;
             const float4 v = r[u];
             if (FIRST) {
-                const int c = e % TC, l4 = (e / TC) * 4;
+                const int c = e / (L / 4), l4 = (e - c * (L / 4)) * 4;
                 const float sc = c < nc ? csign[cur][c] : 0.f;
                 buf[(l4 + 0) * LDT + c] = {v.x * sc * lsign[l4 + 0], 0.f};
                 buf[(l4 + 1) * LDT + c] = {v.y * sc * lsign[l4 + 1], 0.f};
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
         __syncthreads();
         if (FIRST) {
             for (int e = tid; e < L * TC / 2; e += NT) {
-                const int c = e % TC, l2 = (e / TC) * 2;
+                const int c = e / (L / 2), l2 = (e - c * (L / 2)) * 2;
                 if (c < nc) {
                     const cx<float> a = buf[l2 * LDT + c], b = buf[(l2 + 1) * LDT + c];
                     *(float4 *)(Xh + cbase[cur][c] + l2) = {a.re * scale, a.im * scale, b.re * scale, b.im * scale};

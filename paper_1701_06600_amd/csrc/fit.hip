@@ -1,10 +1,10 @@
 // Sampled fit estimate (Section 3.4) and the tensor norm.
 //
-// One thread per sampled entry: it regenerates the entry's multi-index from
-// Philox (so the set is the same at every call), loads the tensor element,
-// evaluates the model entry sum_r lambda_r prod_m A^(m)(i_m, r) from the
-// L2-resident factor rows and squares the error; FP64 throughout, fixed-order
-// block sums, and a one-block final kernel.
+// Each entry's multi-index comes from Philox (so the set is the same at every
+// call) or from the fit set drawn once per run; sixteen lanes evaluate its
+// model entry sum_r lambda_r prod_m A^(m)(i_m, r) from the L2-resident factor
+// rows and the error is squared; FP64 throughout, fixed-order block sums, and
+// the last block (or a one-block kernel) sums the block partials.
 #include <math.h>
 
 #include <type_traits>
@@ -14,6 +14,10 @@
 namespace cprand {
 
 constexpr int kFitThreads = 256;
+constexpr int kFitLanes = 16;
+static_assert(kFitSamplesPerBlock * kMaxOrder % kFitThreads == 0 && kFitSamplesPerBlock * 2 % kFitThreads == 0,
+              "whole staging loads per thread");
+static_assert(kFitSamplesPerBlock % (kFitThreads / kFitLanes) == 0, "whole entries per lane group");
 
 __device__ inline void load_elem(const void *X, int kind, int64_t o, double &re, double &im) {
     im = 0.0;
@@ -64,82 +68,169 @@ hipError_t launch_fit_set(const FitArgs &a, int32_t *frow, double *fx, hipStream
     return hipGetLastError();
 }
 
-// Factor entry (r) of row `row` of mode m, real and imaginary parts.
-__device__ inline void factor_entry(const FitArgs &a, int m, int64_t row, int r, double &ar, double &ai) {
-    const int64_t o = row * a.R + r;
-    if (!a.cplx) {
-        ar = a.fdouble ? ((const double *)a.A.p[m])[o] : (double)((const float *)a.A.p[m])[o];
-        ai = 0.0;
-    } else if (a.fdouble) {
-        ar = ((const double *)a.A.p[m])[2 * o];
-        ai = ((const double *)a.A.p[m])[2 * o + 1];
-    } else {
-        ar = (double)((const float *)a.A.p[m])[2 * o];
-        ai = (double)((const float *)a.A.p[m])[2 * o + 1];
+
+constexpr int kFitGroups = kFitThreads / kFitLanes;          // lane groups per block
+constexpr int kFitJ = kFitSamplesPerBlock / kFitGroups;      // entries per lane group
+
+// Model entries of a lane group's kFitJ entries (grp + kFitGroups j), lane
+// taking ranks lane, lane + 16, ...: per mode, the kFitJ factor loads are
+// issued together (entry indices past the block's last entry are clamped and
+// their sums dropped), FP64 products in the order lambda_r, A^(1), A^(2), ...
+template <typename FT, bool CPLX>
+__device__ __forceinline__ void fit_model(const FitArgs &a, const int32_t *s_row, int ne, int lane, int grp,
+                                          double (&mr)[kFitJ], double (&mi)[kFitJ]) {
+    const int N = a.mi.order, R = a.R;
+#pragma unroll
+    for (int j = 0; j < kFitJ; ++j) mr[j] = mi[j] = 0.0;
+    for (int r = lane; r < R; r += kFitLanes) {
+        double zr[kFitJ], zi[kFitJ];
+        const double lam = a.lambda[r];
+#pragma unroll
+        for (int j = 0; j < kFitJ; ++j) {
+            zr[j] = lam;
+            zi[j] = 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m) {  // static m: the factor pointers are scalar kernel arguments
+            if (m >= N) break;
+            const FT *Am = (const FT *)a.A.p[m];
+            FT vr[kFitJ], vi[kFitJ];
+#pragma unroll
+            for (int j = 0; j < kFitJ; ++j) {
+                const int q = min(grp + kFitGroups * j, ne - 1);
+                const int64_t o = (int64_t)s_row[q * N + m] * R + r;
+                if (CPLX) {
+                    vr[j] = Am[2 * o];
+                    vi[j] = Am[2 * o + 1];
+                } else {
+                    vr[j] = Am[o];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kFitJ; ++j) {
+                if (CPLX) {
+                    const double ar = (double)vr[j], ai = (double)vi[j];
+                    const double nr = zr[j] * ar - zi[j] * ai, ni = zr[j] * ai + zi[j] * ar;
+                    zr[j] = nr;
+                    zi[j] = ni;
+                } else {
+                    zr[j] *= (double)vr[j];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kFitJ; ++j) {
+            mr[j] += zr[j];
+            mi[j] += zi[j];
+        }
     }
 }
 
+// A block takes kFitSamplesPerBlock entries: their rows and tensor values are
+// staged in LDS with coalesced loads (or drawn from Philox), then each group
+// of sixteen lanes evaluates sixteen entries, lane k taking ranks k, k + 16,
+// ...: the factor loads of all sixteen entries are independent, so they are
+// in flight together, and the entry sums are closed with lane shuffles.
+// Few blocks keep the ticket counter of the single-launch finish cheap.
 __global__ __launch_bounds__(kFitThreads) void fit_partial_kernel(FitArgs a) {
     __shared__ double sh[kFitThreads / kWave];
     __shared__ int s_last;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double e2 = 0.0;
-    if (p < a.P_hat) {
-        const int N = a.mi.order;
+    __shared__ int32_t s_row[kFitSamplesPerBlock * kMaxOrder];
+    __shared__ double s_x[kFitSamplesPerBlock * 2];
+    const int tid = threadIdx.x;
+    const int N = a.mi.order;
+    const int64_t p0 = (int64_t)blockIdx.x * kFitSamplesPerBlock;
+    const int ne = (int)min((int64_t)kFitSamplesPerBlock, (int64_t)a.P_hat - p0);
+    // State copy: word g of every segment (factors, then lambda) is loaded
+    // here, with the staging loads, and stored after them; words past the
+    // grid's size go in a plain loop.  Iteration *t_dev is read before this
+    // block takes its ticket, so before the last block advances it.
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + tid, gs = (int64_t)gridDim.x * blockDim.x;
+    const int nseg = a.snap.nsrc > 0 ? a.snap.nsrc + 1 : 0;
+    uint32_t snapv[kMaxOrder + 1];
+    uint64_t snap_t = 0;
+    if (nseg > 0) snap_t = *a.t_dev;
+#pragma unroll
+    for (int m = 0; m <= kMaxOrder; ++m) {
+        if (m >= nseg) break;
+        const uint32_t *src = (const uint32_t *)(m < a.snap.nsrc ? a.snap.src[m] : (const void *)a.snap.lambda);
+        const int64_t w = m < a.snap.nsrc ? a.snap.words[m] : 2 * (int64_t)a.snap.R;
+        snapv[m] = g < w ? src[g] : 0u;
+    }
+    if (a.frow) {  // every load of the staging in flight at once
+        constexpr int kRowLoads = kFitSamplesPerBlock * kMaxOrder / kFitThreads;
+        constexpr int kXLoads = kFitSamplesPerBlock * 2 / kFitThreads;
+        int32_t rv[kRowLoads];
+        double xv[kXLoads];
+#pragma unroll
+        for (int u = 0; u < kRowLoads; ++u) {
+            const int e = tid + u * kFitThreads;
+            rv[u] = e < ne * N ? a.frow[p0 * N + e] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kXLoads; ++u) {
+            const int e = tid + u * kFitThreads;
+            xv[u] = e < 2 * ne ? a.fx[2 * p0 + e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kRowLoads; ++u) s_row[tid + u * kFitThreads] = rv[u];
+#pragma unroll
+        for (int u = 0; u < kXLoads; ++u) s_x[tid + u * kFitThreads] = xv[u];
+    }
+    if (nseg > 0) {
+        uint32_t *dst = (uint32_t *)(snap_t & 1 ? a.snap.dst1 : a.snap.dst0);
+        int64_t off = 0;
+#pragma unroll
+        for (int m = 0; m <= kMaxOrder; ++m) {
+            if (m >= nseg) break;
+            const uint32_t *src = (const uint32_t *)(m < a.snap.nsrc ? a.snap.src[m] : (const void *)a.snap.lambda);
+            const int64_t w = m < a.snap.nsrc ? a.snap.words[m] : 2 * (int64_t)a.snap.R;
+            if (g < w) dst[off + g] = snapv[m];
+            for (int64_t e = g + gs; e < w; e += gs) dst[off + e] = src[e];
+            off += w;
+        }
+    }
+    if (!a.frow && tid < ne) {
         int64_t row[kMaxOrder];
         double xr, xi;
-        if (a.frow) {
-            for (int k = 0; k < N; ++k) row[k] = a.frow[p * N + k];
-            xr = a.fx[2 * p];
-            xi = a.fx[2 * p + 1];
-        } else {
-            fit_entry(a, p, row, xr, xi);
+        fit_entry(a, p0 + tid, row, xr, xi);
+#pragma unroll
+        for (int k = 0; k < kMaxOrder; ++k)
+            if (k < N) s_row[tid * N + k] = (int32_t)row[k];
+        s_x[2 * tid] = xr;
+        s_x[2 * tid + 1] = xi;
+    }
+    __syncthreads();
+    // model entries sum_r lambda_r prod_m A^(m)(i_m, r) of entries grp + 16 j
+    const int lane = tid & (kFitLanes - 1), grp = tid / kFitLanes;
+    double mr[kFitJ], mi[kFitJ];
+    if (a.cplx) {
+        if (a.fdouble)
+            fit_model<double, true>(a, s_row, ne, lane, grp, mr, mi);
+        else
+            fit_model<float, true>(a, s_row, ne, lane, grp, mr, mi);
+    } else {
+        if (a.fdouble)
+            fit_model<double, false>(a, s_row, ne, lane, grp, mr, mi);
+        else
+            fit_model<float, false>(a, s_row, ne, lane, grp, mr, mi);
+    }
+    double e2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < kFitJ; ++j) {
+#pragma unroll
+        for (int off = kFitLanes / 2; off > 0; off >>= 1) {
+            mr[j] += __shfl_xor(mr[j], off, kFitLanes);
+            mi[j] += __shfl_xor(mi[j], off, kFitLanes);
         }
-        // model entry sum_r lambda_r prod_m A^(m)(i_m, r), four ranks at a time
-        // so that their factor loads are in flight together (same order of
-        // operations as one rank at a time)
-        double mr = 0.0, mi = 0.0;
-        for (int r0 = 0; r0 < a.R; r0 += 4) {
-            double zr[4], zi[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                zr[u] = r0 + u < a.R ? a.lambda[r0 + u] : 0.0;
-                zi[u] = 0.0;
-            }
-#pragma unroll
-            for (int m = 0; m < kMaxOrder; ++m) {
-                if (m >= N) break;
-                double ar[4], ai[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (r0 + u < a.R)
-                        factor_entry(a, m, row[m], r0 + u, ar[u], ai[u]);
-                    else
-                        ar[u] = ai[u] = 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (!a.cplx) {
-                        zr[u] *= ar[u];
-                    } else {
-                        const double nr = zr[u] * ar[u] - zi[u] * ai[u], ni = zr[u] * ai[u] + zi[u] * ar[u];
-                        zr[u] = nr;
-                        zi[u] = ni;
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (r0 + u < a.R) {
-                    mr += zr[u];
-                    mi += zi[u];
-                }
+        const int q = grp + kFitGroups * j;
+        if (lane == 0 && q < ne) {
+            const double dr = s_x[2 * q] - mr[j], di = s_x[2 * q + 1] - mi[j];
+            e2 += dr * dr + di * di;
         }
-        const double dr = xr - mr, di = xi - mi;
-        e2 = dr * dr + di * di;
     }
     const double s = block_sum<kFitThreads>(e2, sh);
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         a.part[blockIdx.x] = s;
         s_last = 0;
         if (a.counter) {
@@ -152,14 +243,13 @@ __global__ __launch_bounds__(kFitThreads) void fit_partial_kernel(FitArgs a) {
         }
     }
     __syncthreads();
-    if (s_last && threadIdx.x < kWave) {
+    if (s_last) {
         __threadfence();
         const volatile double *vp = a.part;
         double tot = 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += kWave) tot += vp[b];
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) tot += __shfl_down(tot, off, kWave);
-        if (threadIdx.x == 0) {
+        for (unsigned b = tid; b < gridDim.x; b += kFitThreads) tot += vp[b];
+        tot = block_sum<kFitThreads>(tot, sh);
+        if (tid == 0) {
             const double f = 1.0 - sqrt(a.P * (tot / (double)a.P_hat)) / *a.normX;
             const uint64_t t = a.t_dev ? *a.t_dev : 0;
             if (a.fit_out) *a.fit_out = f;
@@ -172,18 +262,20 @@ __global__ __launch_bounds__(kFitThreads) void fit_partial_kernel(FitArgs a) {
 }
 
 hipError_t launch_fit_partial(const FitArgs &a, int32_t *nblocks, hipStream_t st) {
-    const int nb = (int)ceil_div(a.P_hat, kFitThreads);
+    const int nb = (int)fit_partials(a.P_hat);
     *nblocks = nb;
     hipLaunchKernelGGL(fit_partial_kernel, dim3(nb), dim3(kFitThreads), 0, st, a);
     return hipGetLastError();
 }
 
-__global__ void fit_final_kernel(const double *part, int32_t nparts, int32_t P_hat, double P,
-                                 const double *normX, double *fit_out, double *hist,
-                                 const uint64_t *t_dev) {
-    if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(kFitThreads) void fit_final_kernel(const double *part, int32_t nparts, int32_t P_hat,
+                                                               double P, const double *normX, double *fit_out,
+                                                               double *hist, const uint64_t *t_dev) {
+    __shared__ double sh[kFitThreads / kWave];
     double s = 0.0;
-    for (int i = 0; i < nparts; ++i) s += part[i];
+    for (int i = threadIdx.x; i < nparts; i += kFitThreads) s += part[i];
+    s = block_sum<kFitThreads>(s, sh);
+    if (threadIdx.x != 0) return;
     const double mu = s / (double)P_hat;
     const double f = 1.0 - sqrt(P * mu) / *normX;
     if (fit_out) *fit_out = f;
@@ -193,7 +285,7 @@ __global__ void fit_final_kernel(const double *part, int32_t nparts, int32_t P_h
 hipError_t launch_fit_final(const double *part, int32_t nparts, int32_t P_hat, double P,
                             const double *normX, double *fit_out, double *hist,
                             const uint64_t *t_dev, hipStream_t st) {
-    hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(64), 0, st, part, nparts, P_hat, P, normX,
+    hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(kFitThreads), 0, st, part, nparts, P_hat, P, normX,
                        fit_out, hist, t_dev);
     return hipGetLastError();
 }
@@ -317,27 +409,6 @@ __global__ void fill_u64_kernel(uint64_t *p, uint64_t v) {
 __global__ void inc_u64_kernel(uint64_t *p) {
     if (threadIdx.x == 0) *p += 1;
 }
-// Copy the factors and lambda after an outer iteration into one of two
-// buffers, chosen by the iteration just finished ((*t_dev - 1) mod 2): the
-// loop can launch the next iteration before it reads this one's fit estimate.
-__global__ __launch_bounds__(256) void snapshot_kernel(SnapArgs a) {
-    const uint64_t t = *a.t_dev - 1;
-    uint32_t *dst = (uint32_t *)(t & 1 ? a.dst1 : a.dst0);
-    int64_t off = 0;
-    for (int m = 0; m <= a.nsrc; ++m) {
-        const uint32_t *src = (const uint32_t *)(m < a.nsrc ? a.src[m] : (const void *)a.lambda);
-        const int64_t w = m < a.nsrc ? a.words[m] : 2 * (int64_t)a.R;
-        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < w; e += (int64_t)gridDim.x * blockDim.x)
-            dst[off + e] = src[e];
-        off += w;
-    }
-}
-
-hipError_t launch_snapshot(const SnapArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(snapshot_kernel, dim3(32), dim3(256), 0, st, a);
-    return hipGetLastError();
-}
-
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, hipStream_t st) {
     hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, p, v);
     return hipGetLastError();

@@ -121,18 +121,30 @@ struct StepArgs {
     const float *Wref;      // refinement partials or NULL
     int32_t wrefparts;
     int64_t rps, rsi, rsr;
-    void *A;                // row-major In x R, real type
+    void *A;                // row-major In x R, real type (not written under mixing)
     void *Ahat;             // MIX: row-major In x R complex
     double *lambda;
     int32_t *info;          // set to CPRAND_W_PINV when the pseudo-inverse was used
 };
-size_t step_finish_lds(int32_t In, int32_t R, bool mix, bool dbl);
-hipError_t launch_step_finish(const StepArgs &a, const FftPlan *fp, bool dbl, hipStream_t st);
+size_t step_finish_lds(int32_t In, int32_t R, bool mix);
+// Under mixing only A-hat and lambda are written (A is left untouched).
+hipError_t launch_step_finish(const StepArgs &a, bool dbl, hipStream_t st);
 hipError_t launch_normalize(int32_t In, int32_t R, void *A, bool adouble,
                             const double *colsq_part, int32_t nblocks, double *lambda,
                             hipStream_t st);
 
 // ---- fit ------------------------------------------------------------------------------
+// The state after an outer iteration, copied into one of two buffers chosen
+// by the parity of the iteration: the loop can launch the next iteration
+// before it reads this one's fit estimate, and undo it from the copy.
+struct SnapArgs {
+    const void *src[kMaxOrder];   // factors (4-byte words each: words[m])
+    int64_t words[kMaxOrder];
+    int32_t nsrc;                 // 0: no copy
+    const double *lambda;         // R doubles, stored after the factors
+    int32_t R;
+    void *dst0, *dst1;            // by the parity of the iteration (even / odd)
+};
 struct FitArgs {
     ModeInfo mi;          // dims/strides of X (n unused)
     const void *X;
@@ -161,9 +173,15 @@ struct FitArgs {
     // from Philox and loaded from X.
     const int32_t *frow;
     const double *fx;
+    // Optional copy of the iteration's state (iteration *t_dev, before the
+    // advance), spread over all blocks.
+    SnapArgs snap;
 };
 // Draw the fit set once (rows and tensor values) for FitArgs::frow / fx.
 hipError_t launch_fit_set(const FitArgs &a, int32_t *frow, double *fx, hipStream_t st);
+// Block partials of the fit estimate: one per kFitSamplesPerBlock entries.
+constexpr int kFitSamplesPerBlock = 256;
+inline int64_t fit_partials(int64_t P_hat) { return (P_hat < 1 ? 1 : P_hat + kFitSamplesPerBlock - 1) / kFitSamplesPerBlock; }
 hipError_t launch_fit_partial(const FitArgs &a, int32_t *nblocks, hipStream_t st);
 // fit_out = 1 - sqrt(P * sum(part)/P_hat) / *normX; also hist[t] (t from t_dev) if hist.
 hipError_t launch_fit_final(const double *part, int32_t nparts, int32_t P_hat, double P,
@@ -203,16 +221,6 @@ hipError_t launch_layout_copy(const ModeInfo &xi, const void *X, int xkind, int3
 
 // ---- small helpers ---------------------------------------------------------------------
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, hipStream_t st);
-struct SnapArgs {
-    const void *src[kMaxOrder];   // factors (4-byte words each: words[m])
-    int64_t words[kMaxOrder];
-    int32_t nsrc;
-    const double *lambda;         // R doubles, stored after the factors
-    int32_t R;
-    void *dst0, *dst1;            // by the parity of the iteration just finished
-    const uint64_t *t_dev;
-};
-hipError_t launch_snapshot(const SnapArgs &a, hipStream_t st);
 hipError_t launch_inc_u64(uint64_t *p, hipStream_t st);
 
 }  // namespace cprand

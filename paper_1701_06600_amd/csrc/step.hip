@@ -1,11 +1,19 @@
 // Everything after the gather of one mode step, in one workgroup, when the
-// mode's I_n x R blocks fit in LDS: sum the MTTKRP and Gram partials, (MIX)
-// unmix the product with D_n F_n^* (Alg. 4 unmix, applied to the I_n x R
-// product), invert V (FP64), solve A = W V^{-1} (Alg. 3), optionally refine
-// once against FP32 data, normalise the columns into lambda, and (MIX) remix
-// the new factor, A-hat = F_n D_n A (Alg. 4).  Replaces five launches per
-// mode step at the sizes where the step is latency-bound.
-#include "fft_device.hpp"
+// mode's I_n x R blocks fit in LDS: sum the MTTKRP and Gram partials, invert V
+// (FP64), solve A = W V^{-1} (Alg. 3), optionally refine once against FP32
+// data, and normalise the columns into lambda.  Replaces five launches per mode
+// step at the sizes where the step is latency-bound.
+//
+// Under mixing the step stays in the mixed domain and needs no FFT.  With Y
+// the I_n x R product of the mixed fibers and the conjugated mixed KRP rows,
+// the real-constrained solution is A = Re(D_n F_n^* Y) V^{-1} (Alg. 4 unmix,
+// eq. rcLS), and its remix A-hat = F_n D_n A (Alg. 4) equals
+// (Z + P conj(Z)) / 2 with Z = Y V^{-1} and P the index reversal
+// k -> (I_n - k) mod I_n: F_n D_n conj(D_n F_n^* Z) = F_n^2 conj(Z) because
+// D_n is a real +-1 diagonal and the unitary DFT is symmetric, and F_n^2 = P.
+// The column norms of A equal those of A-hat (unitary mixing), so lambda and
+// the normalised A-hat come straight from Z.  The real factor is not formed
+// here; the caller unmixes A-hat once when it needs A.
 #include "kernels.hpp"
 #include "solve_device.hpp"
 
@@ -29,7 +37,7 @@ __device__ inline float vget(const float4 &v, int u) { return u == 0 ? v.x : u =
 __device__ inline double vget(const double2 &v, int u) { return u == 0 ? v.x : v.y; }
 
 template <typename T>
-__global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a, FftPlan fp) {
+__global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int In = a.In, R = a.R, ld = R + 1;
     const int tid = threadIdx.x;
@@ -39,11 +47,10 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a, F
     double *cs = B3 + R * ld;            // 66
     double *tmp = cs + 66;               // max(R, kColParts * R)
     int *pairs = (int *)(tmp + kColParts * kMaxRank);  // 66
-    double *Wd = (double *)(pairs + 68); // In x R
-    double *Ad = Wd + (size_t)In * R;    // In x R
-    cx<T> *t0 = (cx<T> *)(Ad + (size_t)In * R);  // MIX: In x ld, twice, + twiddles
-    cx<T> *t1 = t0 + (size_t)In * ld;
-    cx<T> *tw = t1 + (size_t)In * ld;
+    double *Wd = (double *)(pairs + 68); // In x R: W (MIX: Re Y)
+    double *Ad = Wd + (size_t)In * R;    // In x R: A (MIX: Re A-hat)
+    double *Wi = Ad + (size_t)In * R;    // MIX: Im Y
+    double *Ai = Wi + (size_t)In * R;    // MIX: Im A-hat
 
     // Partial products (at most kMaxParts) are added in partial order; the
     // loads of one element are issued together, two elements per pass.
@@ -102,10 +109,10 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a, F
                         re += (double)vget(vr[p], u);
                         im += (double)vget(vi[p], u);
                     }
-                t0[(l0 + u) * ld + c] = {(T)re, (T)im};
+                Wd[(l0 + u) * R + c] = re;
+                Wi[(l0 + u) * R + c] = im;
             }
         }
-        for (int e = tid; e < In; e += kStepThreads) tw[e] = ((const cx<T> *)fp.tw)[e];
     } else if (!a.mix) {
         const T *w = (const T *)a.W;
         for (int e0 = tid; e0 < In * R; e0 += 2 * kStepThreads) {
@@ -156,22 +163,75 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a, F
                         re += (double)vr[h][p];
                         im += (double)vi[h][p];
                     }
-                if (e < In * R) t0[l * ld + c] = {(T)re, (T)im};
+                if (e < In * R) {
+                    Wd[l * R + c] = re;
+                    Wi[l * R + c] = im;
+                }
             }
         }
-        for (int e = tid; e < In; e += kStepThreads) tw[e] = ((const cx<T> *)fp.tw)[e];
     }
     __syncthreads();
     const int failed = spd_inverse(B1, B2, B3, tmp, R, ld, cs, pairs);
     if (tid == 0 && a.info && failed) *a.info = CPRAND_W_PINV;
-    const T scale = (T)(1.0 / sqrt((double)In));
     if (a.mix) {
-        const cx<T> *res = fft_tile_rt<T, 1>(t0, t1, fp, ld, R, tw);
-        for (int e = tid; e < In * R; e += kStepThreads) {
-            const int l = e / R, c = e - l * R;
-            Wd[e] = (double)((T)a.sign[l] * res[l * ld + c].re * scale);
+        // Y_s = (Y + P conj Y) / 2 in place: rows k and I_n - k form a pair
+        // (rows 0 and I_n / 2 pair with themselves), one thread per pair
+        const int half = In / 2 + 1;
+        for (int e = tid; e < half * R; e += kStepThreads) {
+            const int k = e / R, r = e - k * R;
+            const int kk = k == 0 ? 0 : In - k;
+            const double yr = Wd[k * R + r], yi = Wi[k * R + r];
+            const double zr = Wd[kk * R + r], zi = Wi[kk * R + r];
+            const double sr = 0.5 * (yr + zr), si = 0.5 * (yi - zi);
+            Wd[k * R + r] = sr;
+            Wi[k * R + r] = si;
+            if (kk != k) {
+                Wd[kk * R + r] = sr;
+                Wi[kk * R + r] = -si;
+            }
         }
         __syncthreads();
+        // A-hat (unnormalised) = Y_s V^{-1}; row I_n - k is the conjugate of row k
+        for (int e = tid; e < half * R; e += kStepThreads) {
+            const int k = e / R, r = e - k * R;
+            const int kk = k == 0 ? 0 : In - k;
+            double sr = 0.0, si = 0.0;
+            for (int j = 0; j < R; ++j) {
+                const double h = B1[j * ld + r];
+                sr += Wd[k * R + j] * h;
+                si += Wi[k * R + j] * h;
+            }
+            Ad[k * R + r] = sr;
+            Ai[k * R + r] = si;
+            if (kk != k) {
+                Ad[kk * R + r] = sr;
+                Ai[kk * R + r] = -si;
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < kColParts * R; e += kStepThreads) {
+            const int r = e / kColParts, part = e - r * kColParts;
+            double s = 0.0;
+            for (int i = part; i < In; i += kColParts) s += Ad[i * R + r] * Ad[i * R + r] + Ai[i * R + r] * Ai[i * R + r];
+            tmp[r * kColParts + part] = s;
+        }
+        __syncthreads();
+        if (tid < R) {
+            double s = 0.0;
+            for (int part = 0; part < kColParts; ++part) s += tmp[tid * kColParts + part];
+            const double l = sqrt(s);
+            B2[tid] = l;
+            a.lambda[tid] = l;
+        }
+        __syncthreads();
+        T *Ah = (T *)a.Ahat;
+        for (int e = tid; e < In * R; e += kStepThreads) {
+            const double l = B2[e % R];
+            const double q = l > 0.0 ? 1.0 / l : 1.0;
+            Ah[2 * (size_t)e] = (T)(Ad[e] * q);
+            Ah[2 * (size_t)e + 1] = (T)(Ai[e] * q);
+        }
+        return;
     }
     for (int e = tid; e < In * R; e += kStepThreads) {
         const int i = e / R, r = e - i * R;
@@ -227,40 +287,25 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a, F
         const int r = e % R;
         const double l = B2[r];
         const T v = (T)Ad[e];
-        const T nv = l > 0.0 ? (T)((double)v / l) : v;
-        A[e] = nv;
-        if (a.mix) t0[(e / R) * ld + r] = {(T)a.sign[e / R] * nv, (T)0};
-    }
-    if (a.mix) {
-        __syncthreads();
-        const cx<T> *res = fft_tile_rt<T, -1>(t0, t1, fp, ld, R, tw);
-        T *Ah = (T *)a.Ahat;
-        for (int e = tid; e < In * R; e += kStepThreads) {
-            const int l = e / R, c = e - l * R;
-            const cx<T> v = res[l * ld + c];
-            Ah[2 * (size_t)e] = v.re * scale;
-            Ah[2 * (size_t)e + 1] = v.im * scale;
-        }
+        A[e] = l > 0.0 ? (T)((double)v / l) : v;
     }
 }
 
-size_t step_finish_lds(int32_t In, int32_t R, bool mix, bool dbl) {
+size_t step_finish_lds(int32_t In, int32_t R, bool mix) {
     const size_t ld = (size_t)R + 1;
     size_t b = sizeof(double) * (3 * (size_t)R * ld + 66 + (size_t)kColParts * kMaxRank) + sizeof(int) * 68;
-    b += sizeof(double) * 2 * (size_t)In * R;
-    if (mix) b += (dbl ? 16 : 8) * ((size_t)2 * In * ld + In);
+    b += sizeof(double) * (mix ? 4 : 2) * (size_t)In * R;
     return b;
 }
 
-hipError_t launch_step_finish(const StepArgs &a, const FftPlan *fp, bool dbl, hipStream_t st) {
+hipError_t launch_step_finish(const StepArgs &a, bool dbl, hipStream_t st) {
     if (a.vparts > kMaxParts || a.wparts > kMaxParts || (a.Wref && a.wrefparts > kMaxParts)) return hipErrorInvalidValue;
-    const size_t lds = step_finish_lds(a.In, a.R, a.mix, dbl);
-    FftPlan f{};
-    if (fp) f = *fp;
+    if (a.mix && !a.Ahat) return hipErrorInvalidValue;
+    const size_t lds = step_finish_lds(a.In, a.R, a.mix);
     if (dbl)
-        hipLaunchKernelGGL(step_finish_kernel<double>, dim3(1), dim3(kStepThreads), lds, st, a, f);
+        hipLaunchKernelGGL(step_finish_kernel<double>, dim3(1), dim3(kStepThreads), lds, st, a);
     else
-        hipLaunchKernelGGL(step_finish_kernel<float>, dim3(1), dim3(kStepThreads), lds, st, a, f);
+        hipLaunchKernelGGL(step_finish_kernel<float>, dim3(1), dim3(kStepThreads), lds, st, a);
     return hipGetLastError();
 }
 

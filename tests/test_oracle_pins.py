@@ -215,6 +215,35 @@ def test_mixed_unsampled_ls_is_real_and_equals_unmixed():
     assert np.allclose(np.linalg.solve(V, W.T).T, plain)
 
 
+def test_mixed_step_needs_no_fft():
+    """The remixed solution of the real-constrained sampled LS (Alg. 4, eq.
+    rcLS) in closed form: with Y = X-hat_S conj(Z-hat_S) and Z = Y V^{-1},
+    F D Re(D F^* Z) = (Z + P conj Z) / 2, P the index reversal k -> -k mod I_n
+    (the DFT is symmetric and F^2 = P).  Column norms agree across the mix.
+    Odd and even I_n (the self-paired rows differ)."""
+    rng = np.random.default_rng(21)
+    for dims in [(7, 5, 6), (8, 5, 6)]:
+        R, n = 3, 0
+        A = _rand_factors(rng, dims, R)
+        X = rng.standard_normal(dims)
+        signs = philox.sign_vectors(dims, 8)
+        Xh = C.mix_tensor(X, signs)
+        Ah = [C.mix_factor(A[m], signs[m]) for m in range(3)]
+        idx = philox.sample_indices(dims, n, 12, 8, 0)
+        Wr, V = C.mixed_normal_blocks(Xh, idx, Ah, n, signs[n])
+        ref_A, ref_lam = C.normalize(C.mixed_sampled_ls(Xh, idx, Ah, n, signs[n]))
+        ref = C.mix_factor(ref_A, signs[n])
+        Y = C.sample_fibers(Xh, idx, n) @ np.conj(C.skr(idx, Ah, n))
+        assert np.allclose(C.unmix_factor(Y, signs[n]).real, Wr)
+        Z = Y @ np.linalg.inv(V)
+        rev = (-np.arange(dims[n])) % dims[n]
+        Ahat = 0.5 * (Z + np.conj(Z[rev]))
+        lam = np.linalg.norm(Ahat, axis=0)
+        assert np.allclose(lam, ref_lam, rtol=1e-12)
+        assert np.allclose(Ahat / lam, ref, rtol=1e-10, atol=1e-12)
+        assert np.abs(Ahat[0].imag).max() < 1e-15
+
+
 def test_mix_factor_roundtrip():
     rng = np.random.default_rng(10)
     A = rng.standard_normal((50, 4))
