@@ -72,6 +72,50 @@ struct KArgs {
     int32_t R, S, In, ncols, kc, rows_wg;
 };
 
+// Fiber values of one MFMA batch: lane (li, lk) takes sample ks + 4u + lk
+// (u < kUnroll) and rows row0 .. row0 + VE - 1 of its mode-n fiber.
+template <typename T, bool CPLX, bool CONTIG>
+__device__ __forceinline__ void load_fibers(T (&v)[kUnroll][16 / sizeof(T)], const T *xp, const int64_t *s_base,
+                                            int ns, int ks, int row0, int lk, int In, int64_t sn) {
+    typedef Geo<T, CPLX> G;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const int sl = ks + 4 * u + lk;
+#pragma unroll
+        for (int e = 0; e < G::NV; ++e) v[u][e] = (T)0;
+        if (sl < ns && row0 < In) {
+            const int64_t b = s_base[sl];
+            if (CONTIG && row0 + G::VE <= In) {
+                const T *src = xp + (b + row0) * (CPLX ? 2 : 1);
+                if (sizeof(T) == 4) {
+                    const float4 q = *(const float4 *)src;
+                    v[u][0] = q.x;
+                    v[u][1] = q.y;
+                    v[u][2] = q.z;
+                    v[u][3] = q.w;
+                } else {
+                    const double2 q = *(const double2 *)src;
+                    v[u][0] = q.x;
+                    v[u][1] = q.y;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < G::VE; ++c) {
+                    if (row0 + c < In) {
+                        const int64_t o = b + (int64_t)(row0 + c) * sn;
+                        if (CPLX) {
+                            v[u][2 * c] = xp[2 * o];
+                            v[u][2 * c + 1] = xp[2 * o + 1];
+                        } else {
+                            v[u][c] = xp[o];
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <typename T, bool CPLX, int CT, bool CONTIG, bool WEIGHTED>
 __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
     typedef Geo<T, CPLX> G;
@@ -135,6 +179,17 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
     }
     __syncthreads();
 
+    // ---- fiber loads (phase 4 below): the first batch of this wave's first
+    // row group is issued now, so its latency overlaps the Khatri-Rao loads
+    const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+    const int In = a.In;
+    const int row_end = min(In, (int)(blockIdx.x + 1) * a.rows_wg);
+    const T *xp = (const T *)a.X;
+    const int64_t sn = a.mi.strides[n];
+    T v[kUnroll][G::NV];
+    const int rb0 = blockIdx.x * a.rows_wg + wv * G::RPW;
+    if (rb0 < row_end) load_fibers<T, CPLX, CONTIG>(v, xp, s_base, ns, 0, rb0 + G::VE * li, lk, In, sn);
+
     // ---- (2) sampled Khatri-Rao rows
     for (int e = tid; e < ns * R; e += nthr) {
         const int sl = e / R, r = e - sl * R;
@@ -168,39 +223,51 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
     }
     __syncthreads();
 
-    // ---- (3) Gram of the chunk (first row block only), FP64, fixed order
-    if (blockIdx.x == 0) {
+    // ---- (3) Gram of the chunk, FP64, fixed order.  Entries p = (r, q) of
+    // the R x R matrix are dealt to the chunk's row blocks (p mod row
+    // blocks); tpp lanes share an entry, each summing every tpp-th sample,
+    // and a shuffle tree over the tpp lanes closes the sum.
+    {
+        const int nrb = (int)gridDim.x, rb = (int)blockIdx.x;
+        const int nmine = (R * R - rb + nrb - 1) / nrb;  // entries of this block
+        int tpp = 1;
+        while (tpp < 16 && 2 * tpp * nmine <= nthr) tpp *= 2;
+        const int per = nthr / tpp;  // entries per pass
         double *vp = a.vpart + (size_t)chunk * R * R;
-        for (int p = tid; p < R * R; p += nthr) {
-            const int r = p / R, q = p - r * R;
-            if (q < r) continue;
+        for (int base = 0; base < nmine; base += per) {
+            const int k = base + tid / tpp, part = tid & (tpp - 1);
+            const int p = rb + nrb * k;
+            const int r = p / R, q = p - (p / R) * R;
+            const bool act = k < nmine && q >= r;
             double acc = 0.0;
-            for (int sl = 0; sl < ns; ++sl) {
-                if (!CPLX) {
-                    double v = (double)Zr[sl * LDB + r] * (double)Zr[sl * LDB + q];
-                    if (WEIGHTED) v *= s_w[sl];
-                    acc += v;
-                } else {
-                    acc += (double)Bre[sl * LDB + r] * (double)Bre[sl * LDB + q] +
-                           (double)Bim[sl * LDB + r] * (double)Bim[sl * LDB + q];
+            if (act) {
+                for (int sl = part; sl < ns; sl += tpp) {
+                    if (!CPLX) {
+                        double t = (double)Zr[sl * LDB + r] * (double)Zr[sl * LDB + q];
+                        if (WEIGHTED) t *= s_w[sl];
+                        acc += t;
+                    } else {
+                        acc += (double)Bre[sl * LDB + r] * (double)Bre[sl * LDB + q] +
+                               (double)Bim[sl * LDB + r] * (double)Bim[sl * LDB + q];
+                    }
                 }
             }
-            vp[r * R + q] = acc;
-            vp[q * R + r] = acc;
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1)
+                if (o < tpp) acc += __shfl_xor(acc, o, 64);  // uniform: tpp is the same in every lane
+            if (act && part == 0) {
+                vp[r * R + q] = acc;
+                vp[q * R + r] = acc;
+            }
         }
     }
 
     // ---- (4) fibers x Z_S on MFMA, one row group of G::RPW rows per wave at a
     // time (a workgroup covers rows_wg rows: one group per wave for short
     // sample chunks, whole fibers for long ones)
-    const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
-    const int In = a.In;
-    const int row_end = min(In, (int)(blockIdx.x + 1) * a.rows_wg);
-    const T *xp = (const T *)a.X;
-    const int64_t sn = a.mi.strides[n];
     T *wp = (T *)a.wpart + (size_t)chunk * a.ncols * In;
-    for (int rowbase = blockIdx.x * a.rows_wg + wv * G::RPW; rowbase < row_end;
-         rowbase += (int)(blockDim.x >> 6) * G::RPW) {
+    bool preloaded = rb0 < row_end;
+    for (int rowbase = rb0; rowbase < row_end; rowbase += (int)(blockDim.x >> 6) * G::RPW) {
     const int row0 = rowbase + G::VE * li;
 
     Acc acc[CT][G::VE];
@@ -210,43 +277,8 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
         for (int c = 0; c < G::VE; ++c) acc[ct][c] = Acc{0, 0, 0, 0};
 
     for (int ks = 0; ks < ns; ks += 4 * kUnroll) {
-        T v[kUnroll][G::NV];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int sl = ks + 4 * u + lk;
-#pragma unroll
-            for (int e = 0; e < G::NV; ++e) v[u][e] = (T)0;
-            if (sl < ns && row0 < In) {
-                const int64_t b = s_base[sl];
-                if (CONTIG && row0 + G::VE <= In) {
-                    const T *src = xp + (b + row0) * (CPLX ? 2 : 1);
-                    if (sizeof(T) == 4) {
-                        const float4 q = *(const float4 *)src;
-                        v[u][0] = q.x;
-                        v[u][1] = q.y;
-                        v[u][2] = q.z;
-                        v[u][3] = q.w;
-                    } else {
-                        const double2 q = *(const double2 *)src;
-                        v[u][0] = q.x;
-                        v[u][1] = q.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < G::VE; ++c) {
-                        if (row0 + c < In) {
-                            const int64_t o = b + (int64_t)(row0 + c) * sn;
-                            if (CPLX) {
-                                v[u][2 * c] = xp[2 * o];
-                                v[u][2 * c + 1] = xp[2 * o + 1];
-                            } else {
-                                v[u][c] = xp[o];
-                            }
-                        }
-                    }
-                }
-            }
-        }
+        if (!preloaded) load_fibers<T, CPLX, CONTIG>(v, xp, s_base, ns, ks, row0, lk, In, sn);
+        preloaded = false;
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             if (ks + 4 * u >= ns) break;  // uniform: the rest of this pass is past the chunk
