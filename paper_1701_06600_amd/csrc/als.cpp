@@ -21,19 +21,27 @@ int mix_tensor_impl(const cprand_tensor *X, const cprand_tensor *Xhat, uint64_t 
     const int xk = kind_of(X->dtype);
     const bool dbl = kind_of(Xhat->dtype) == K_C128;
     const ModeInfo mi = mode_info(X, 0);
-    hipError_t e = launch_signs(mi, seed, signs, st);
+    hipError_t e = hipSuccess;
+    FftPlan *fps[CPRAND_MAX_ORDER] = {};
+    for (int m = 0; m < X->order; ++m) {
+        fps[m] = fft_plan_get(X->dims[m], dbl, &e);
+        if (!fps[m]) return set_error(CPRAND_EUNSUPPORTED, "mode %d length %lld does not factor into 2,3,5,7", m,
+                                      (long long)X->dims[m]);
+    }
+    e = launch_signs(mi, seed, signs, st);
     if (e != hipSuccess) return hip_fail(e, "sign kernel");
+    // ||X|| from the first pass when its kernel supports it, else its own pass
     int32_t np = 0;
-    e = launch_normsq_partial(mi, X->data, xk, (double *)workspace, &np, st);
+    for (int m = 0; m < X->order; ++m) {
+        MixExtras ex{};
+        if (m == 0) ex.normsq_part = (double *)workspace;
+        e = launch_mix_pass(fps[m], dbl, mi, X->data, xk, Xhat->data, m, m == 0, signs, &ex, st);
+        if (e != hipSuccess) return hip_fail(e, "mix pass");
+        if (m == 0) np = ex.nparts;
+    }
+    if (np == 0) e = launch_normsq_partial(mi, X->data, xk, (double *)workspace, &np, st);
     if (e == hipSuccess) e = launch_sqrt_sum((double *)workspace, np, normX_out, st);
     if (e != hipSuccess) return hip_fail(e, "norm kernels");
-    for (int m = 0; m < X->order; ++m) {
-        FftPlan *fp = fft_plan_get(X->dims[m], dbl, &e);
-        if (!fp) return set_error(CPRAND_EUNSUPPORTED, "mode %d length %lld does not factor into 2,3,5,7", m,
-                                  (long long)X->dims[m]);
-        e = launch_mix_pass(fp, dbl, mi, X->data, xk, Xhat->data, m, m == 0, signs, nullptr, nullptr, st);
-        if (e != hipSuccess) return hip_fail(e, "mix pass");
-    }
     return CPRAND_OK;
 }
 
@@ -627,22 +635,31 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
     ModeInfo xi = mode_info(X, 0);
     bool timed_mix[CPRAND_MAX_ORDER] = {}, timed_lay[CPRAND_MAX_ORDER] = {};
     hipEvent_t *tev = p->tev;
-    if (e == hipSuccess) {
-        int32_t np = 0;
-        e = hipEventRecord(tev[0], st);
-        if (e == hipSuccess) e = launch_normsq_partial(xi, X->data, p->xkind, p->normpart, &np, st);
-        if (e == hipSuccess) e = launch_sqrt_sum(p->normpart, np, p->normX, st);
-        if (e == hipSuccess) e = hipEventRecord(tev[1], st);
-    }
+    // ||X||: folded into the first mixing pass when its kernel supports it
+    // (it reads all of X anyway), else a pass of its own
+    bool norm_done = false, copied_last = false;
     if (e == hipSuccess && p->mix) {
         e = launch_signs(xi, p->o.seed, p->signs, st);
         for (int m = 0; m < N && e == hipSuccess; ++m) {
             FftPlan *fp = fft_plan_get(p->dims[m], p->dbl, &e);
+            MixExtras ex{};
+            if (m == 0) ex.normsq_part = p->normpart;
+            if (m == N - 1 && p->gview[m].own) {  // the last pass can also write mode m's mode-major copy
+                ex.copy = p->gview[m].data;
+                ex.copy_ld = p->gview[m].ld;
+            }
             if (fp) e = hipEventRecord(tev[2 + 2 * m], st);
             if (fp && e == hipSuccess)
-                e = launch_mix_pass(fp, p->dbl, xi, X->data, p->xkind, p->xhat, m, m == 0, p->signs, nullptr, nullptr, st);
+                e = launch_mix_pass(fp, p->dbl, xi, X->data, p->xkind, p->xhat, m, m == 0, p->signs, &ex, st);
             if (fp && e == hipSuccess) e = hipEventRecord(tev[3 + 2 * m], st);
             timed_mix[m] = e == hipSuccess;
+            if (e == hipSuccess && m == 0 && ex.nparts > 0) {
+                e = hipEventRecord(tev[0], st);
+                if (e == hipSuccess) e = launch_sqrt_sum(p->normpart, ex.nparts, p->normX, st);
+                if (e == hipSuccess) e = hipEventRecord(tev[1], st);
+                norm_done = e == hipSuccess;
+            }
+            if (m == N - 1) copied_last = ex.copied;
         }
         cprand_tensor xh{};
         xh.order = N;
@@ -656,7 +673,7 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
         xh.data = p->xhat;
         ModeInfo hi = mode_info(&xh, 0);
         for (int n = 0; n < N && e == hipSuccess; ++n)
-            if (p->gview[n].own) {
+            if (p->gview[n].own && !(n == N - 1 && copied_last)) {
                 e = hipEventRecord(tev[2 + 2 * N + 2 * n], st);
                 if (e == hipSuccess)
                     e = launch_layout_copy(hi, p->xhat, p->gkind, n, p->gview[n].ld, p->gview[n].data, p->gkind, st);
@@ -679,6 +696,13 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
             if (any && e == hipSuccess) e = hipEventRecord(tev[3 + 2 * N + 2 * n], st);
             timed_lay[n] = any && e == hipSuccess;
         }
+    }
+    if (e == hipSuccess && !norm_done) {
+        int32_t np = 0;
+        e = hipEventRecord(tev[0], st);
+        if (e == hipSuccess) e = launch_normsq_partial(xi, X->data, p->xkind, p->normpart, &np, st);
+        if (e == hipSuccess) e = launch_sqrt_sum(p->normpart, np, p->normX, st);
+        if (e == hipSuccess) e = hipEventRecord(tev[1], st);
     }
     // the fixed fit set: rows and tensor values drawn once per run
     if (e == hipSuccess) e = launch_fit_set(fit_args(p, X->data), p->frow, p->fx, st);

@@ -164,7 +164,8 @@ __global__ __launch_bounds__(NT) void mix_pass_ct(const Tin *X, cx<float> *Xh, i
 // the LDS work.  Same arithmetic and output as mix_pass_ct.
 template <int L, int TC, int NT, bool FIRST>
 __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *Xh, int64_t J, int64_t K, ModeInfo xi,
-                                                    int m, const int8_t *signs, const cx<float> *twg) {
+                                                    int m, const int8_t *signs, const cx<float> *twg,
+                                                    double *normsq_part, cx<float> *copy) {
     constexpr int LDT = TC + 1;
     constexpr int NV = FIRST ? L * TC / 4 : L * TC / 2;  // float4 per tile
     constexpr int PF = (NV + NT - 1) / NT;                // float4 per thread
@@ -235,7 +236,11 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
         }
     };
     int64_t t = blockIdx.x;
-    if (t >= ntiles) return;
+    if (t >= ntiles) {
+        if (FIRST && normsq_part && tid == 0) normsq_part[blockIdx.x] = 0.0;
+        return;
+    }
+    double nacc = 0.0;  // FIRST: sum of squares of the raw input (signs do not change it)
     tile_info(t, 0);
     __syncthreads();
     issue_loads(0, tile_nc(t));
@@ -255,6 +260,7 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
             if (FIRST) {
                 const int c = e / (L / 4), l4 = (e - c * (L / 4)) * 4;
                 const float sc = c < nc ? csign[cur][c] : 0.f;
+                nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
                 buf[(l4 + 0) * LDT + c] = {v.x * sc * lsign[l4 + 0], 0.f};
                 buf[(l4 + 1) * LDT + c] = {v.y * sc * lsign[l4 + 1], 0.f};
                 buf[(l4 + 2) * LDT + c] = {v.z * sc * lsign[l4 + 2], 0.f};
@@ -287,7 +293,22 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
                                                                        b.im * scale};
                 }
             }
+            if (copy) {  // the same fibers again, each stored contiguously (fiber q at copy + q * L)
+                for (int e = tid; e < L * TC / 2; e += NT) {
+                    const int c = e / (L / 2), l2 = (e - c * (L / 2)) * 2;
+                    if (c < nc) {
+                        const cx<float> a = buf[l2 * LDT + c], b = buf[(l2 + 1) * LDT + c];
+                        *(float4 *)(copy + (t * TC + c) * (int64_t)L + l2) = {a.re * scale, a.im * scale,
+                                                                             b.re * scale, b.im * scale};
+                    }
+                }
+            }
         }
+    }
+    if (FIRST && normsq_part) {
+        __shared__ double sh[NT / kWave];
+        nacc = block_sum<NT>(nacc, sh);
+        if (tid == 0) normsq_part[blockIdx.x] = nacc;
     }
 }
 
@@ -374,6 +395,13 @@ static int tile_cols(int64_t L, int esz) {
     if (tc > 16) tc = 16;
     if (tc < 1) tc = 1;
     return (int)tc;
+}
+// Columns per workgroup for the R columns of a factor or mode-step product:
+// at most what fits in LDS, and few enough that about eight workgroups share
+// the R columns (one workgroup per launch would run the FFT stages serially).
+static int tile_cols_for(int64_t L, int esz, int R) {
+    const int per = (R + 7) / 8;
+    return std::max(1, std::min(tile_cols(L, esz), per));
 }
 static size_t tile_lds(int64_t L, int tc, size_t esz) { return (2 * (size_t)L * (tc + 1) + (size_t)L) * esz; }
 
@@ -555,7 +583,7 @@ static int device_cus() {
 
 template <int L, int TC, int NT>
 static hipError_t launch_ct_pass(const FftPlan *fp, const ModeInfo &xi, const void *X, int xkind, void *Xhat, int m,
-                                 bool first, const int8_t *signs, int64_t J, int64_t K, hipStream_t st) {
+                                 bool first, const int8_t *signs, int64_t J, int64_t K, MixExtras *ex, hipStream_t st) {
     const unsigned nb = (unsigned)ceil_div(J * K, TC);
     const cx<float> *tw = (const cx<float> *)fp->tw;
     const bool xa = (((uintptr_t)X) & 15) == 0, ha = (((uintptr_t)Xhat) & 15) == 0;
@@ -578,8 +606,10 @@ static hipError_t launch_ct_pass(const FftPlan *fp, const ModeInfo &xi, const vo
         }
         if constexpr (L % 4 == 0 && kPipe) {
             if (J == 1 && xa && ha) {
+                double *nsp = ex ? ex->normsq_part : nullptr;
                 hipLaunchKernelGGL((mix_pass_pipe<L, TC, NT, true>), dim3(np), dim3(NT), 0, st, (const float *)X,
-                                   (cx<float> *)Xhat, J, K, xi, m, signs, tw);
+                                   (cx<float> *)Xhat, J, K, xi, m, signs, tw, nsp, (cx<float> *)nullptr);
+                if (nsp) ex->nparts = (int32_t)np;
                 return hipGetLastError();
             }
         }
@@ -590,8 +620,11 @@ static hipError_t launch_ct_pass(const FftPlan *fp, const ModeInfo &xi, const vo
     } else {
         if constexpr (kPipe) {
             if (J > 1 && J % TC == 0 && ha) {
+                const bool cp = ex && ex->copy && ex->copy_ld == L && (((uintptr_t)ex->copy) & 15) == 0;
                 hipLaunchKernelGGL((mix_pass_pipe<L, TC, NT, false>), dim3(np), dim3(NT), 0, st,
-                                   (const float *)nullptr, (cx<float> *)Xhat, J, K, xi, m, signs, tw);
+                                   (const float *)nullptr, (cx<float> *)Xhat, J, K, xi, m, signs, tw,
+                                   (double *)nullptr, cp ? (cx<float> *)ex->copy : (cx<float> *)nullptr);
+                if (cp) ex->copied = true;
                 return hipGetLastError();
             }
         }
@@ -608,33 +641,34 @@ static hipError_t launch_ct_pass(const FftPlan *fp, const ModeInfo &xi, const vo
 // Lengths with a compile-time schedule (single precision).
 static bool launch_fixed_length(int64_t L, const FftPlan *fp, const ModeInfo &xi, const void *X, int xkind,
                                 void *Xhat, int m, bool first, const int8_t *signs, int64_t J, int64_t K,
-                                hipStream_t st, hipError_t *err) {
+                                MixExtras *ex, hipStream_t st, hipError_t *err) {
     switch (L) {
-        case 50: *err = launch_ct_pass<50, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
-        case 60: *err = launch_ct_pass<60, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
-        case 90: *err = launch_ct_pass<90, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
-        case 100: *err = launch_ct_pass<100, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
-        case 128: *err = launch_ct_pass<128, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
-        case 150: *err = launch_ct_pass<150, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
-        case 200: *err = launch_ct_pass<200, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
-        case 300: *err = launch_ct_pass<300, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
-        case 400: *err = launch_ct_pass<400, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
-        case 1000: *err = launch_ct_pass<1000, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, st); return true;
+        case 50: *err = launch_ct_pass<50, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
+        case 60: *err = launch_ct_pass<60, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
+        case 90: *err = launch_ct_pass<90, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
+        case 100: *err = launch_ct_pass<100, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
+        case 128: *err = launch_ct_pass<128, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
+        case 150: *err = launch_ct_pass<150, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
+        case 200: *err = launch_ct_pass<200, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
+        case 300: *err = launch_ct_pass<300, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
+        case 400: *err = launch_ct_pass<400, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
+        case 1000: *err = launch_ct_pass<1000, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
         default: return false;
     }
 }
 
 hipError_t launch_mix_pass(const FftPlan *fp, bool dbl, const ModeInfo &xi, const void *X, int xkind, void *Xhat,
-                           int32_t m, bool first, const int8_t *signs, double *normsq_part, int32_t *nparts,
-                           hipStream_t st) {
-    (void)normsq_part;
+                           int32_t m, bool first, const int8_t *signs, MixExtras *ex, hipStream_t st) {
     int64_t J = 1, K = 1;
     for (int i = 0; i < m; ++i) J *= xi.dims[i];
     for (int i = m + 1; i < xi.order; ++i) K *= xi.dims[i];
-    if (nparts) *nparts = 0;
+    if (ex) {
+        ex->nparts = 0;
+        ex->copied = false;
+    }
     if (!dbl && (!first || xkind == K_F32)) {
         hipError_t e;
-        if (launch_fixed_length(fp->L, fp, xi, X, xkind, Xhat, m, first, signs, J, K, st, &e)) return e;
+        if (launch_fixed_length(fp->L, fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st, &e)) return e;
     }
     const size_t esz = dbl ? 16 : 8;
     const int tc = tile_cols(fp->L, (int)esz);
@@ -656,7 +690,7 @@ hipError_t launch_mix_pass(const FftPlan *fp, bool dbl, const ModeInfo &xi, cons
 hipError_t launch_factor_mix(const FftPlan *fp, bool dbl, int32_t I, int32_t R, const void *in, const int8_t *sign,
                              void *out, bool inverse, hipStream_t st) {
     const size_t esz = dbl ? 16 : 8;
-    const int tc = std::min(tile_cols(fp->L, (int)esz), (int)R);
+    const int tc = tile_cols_for(fp->L, (int)esz, (int)R);
     const int nb = (int)ceil_div(R, tc);
     const size_t lds = tile_lds(fp->L, tc, esz);
     if (dbl)
@@ -671,7 +705,7 @@ hipError_t launch_factor_mix(const FftPlan *fp, bool dbl, int32_t I, int32_t R, 
 hipError_t launch_unmix(const FftPlan *fp, bool dbl, int32_t In, int32_t R, int32_t chunks, const void *ypart,
                         const int8_t *sign, void *W, bool w_rowmajor, hipStream_t st) {
     const size_t esz = dbl ? 16 : 8;
-    const int tc = std::min(tile_cols(fp->L, (int)esz), (int)R);
+    const int tc = tile_cols_for(fp->L, (int)esz, (int)R);
     const int nb = (int)ceil_div(R, tc);
     const size_t lds = tile_lds(fp->L, tc, esz);
     if (dbl)

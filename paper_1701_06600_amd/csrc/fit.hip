@@ -390,15 +390,16 @@ hipError_t launch_normsq_partial(const ModeInfo &mi, const void *X, int kind, do
     return hipGetLastError();
 }
 
-__global__ void sqrt_sum_kernel(const double *part, int32_t n, double *out) {
-    if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(256) void sqrt_sum_kernel(const double *part, int32_t n, double *out) {
+    __shared__ double sh[256 / kWave];
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = sqrt(s);
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    s = block_sum<256>(s, sh);
+    if (threadIdx.x == 0) *out = sqrt(s);
 }
 
 hipError_t launch_sqrt_sum(const double *part, int32_t nparts, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(sqrt_sum_kernel, dim3(1), dim3(64), 0, st, part, nparts, out);
+    hipLaunchKernelGGL(sqrt_sum_kernel, dim3(1), dim3(256), 0, st, part, nparts, out);
     return hipGetLastError();
 }
 

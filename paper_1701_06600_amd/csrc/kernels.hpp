@@ -82,9 +82,22 @@ hipError_t launch_factor_mix(const FftPlan *fp, bool dbl, int32_t I, int32_t R, 
 // (any strides), apply all sign vectors and write column-major complex
 // Xhat; otherwise transform Xhat in place.  normsq_part: per-block partial
 // sums of x^2 (first pass only) or NULL.
+// Optional work folded into a mixing pass.  In: normsq_part (first pass:
+// per-workgroup sums of squares of the input, at least 4096 doubles) and
+// copy / copy_ld (a later pass: the pass's output fibers also stored
+// contiguously, fiber q at copy + q * copy_ld, the layout of a mode-major
+// copy).  Out: nparts (partials written, 0 if none) and copied.  Kernels
+// that do not support an item leave it undone and report so.
+struct MixExtras {
+    double *normsq_part;
+    int32_t nparts;
+    void *copy;
+    int64_t copy_ld;
+    bool copied;
+};
 hipError_t launch_mix_pass(const FftPlan *fp, bool dbl, const ModeInfo &xi, const void *X,
                            int xkind, void *Xhat, int32_t m, bool first, const int8_t *signs,
-                           double *normsq_part, int32_t *nparts, hipStream_t st);
+                           MixExtras *ex, hipStream_t st);
 hipError_t launch_signs(const ModeInfo &mi, uint64_t seed, int8_t *signs, hipStream_t st);
 
 // ---- solve / normalise -------------------------------------------------------------

@@ -147,14 +147,8 @@ __device__ inline double bsel(bool c, double a, double b) {
 // l % 16 of rows l / 16 + 4 q (q < 4), and each step fetches the pivot, the
 // pivot column and the pivot row from the owning lanes by shuffles.
 // Returns 1 if a pivot falls below 1e-12 maxdiag (B1 is then untouched).
-__device__ __forceinline__ int gj_wave(double *B1, int R, int ld, double maxdiag) {
-    const int l = threadIdx.x, j = l & 15, i0 = l >> 4;
-    double v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i = i0 + 4 * q;
-        v[q] = (i < R && j < R) ? B1[i * ld + j] : 0.0;
-    }
+__device__ __forceinline__ int gj_wave_regs(double (&v)[4], int R, double maxdiag) {
+    const int l = threadIdx.x & (kWave - 1), j = l & 15, i0 = l >> 4;
     for (int k = 0; k < R; ++k) {
         const int kq = k >> 2;  // slot of row k (uniform)
         const double vk = kq == 0 ? v[0] : kq == 1 ? v[1] : kq == 2 ? v[2] : v[3];
@@ -172,6 +166,46 @@ __device__ __forceinline__ int gj_wave(double *B1, int R, int ld, double maxdiag
             v[q] = bsel(i == k, on_row, bsel(j == k, on_col, other));
         }
     }
+    return 0;
+}
+
+__device__ __forceinline__ int gj_wave(double *B1, int R, int ld, double maxdiag) {
+    const int l = threadIdx.x, j = l & 15, i0 = l >> 4;
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = i0 + 4 * q;
+        v[q] = (i < R && j < R) ? B1[i * ld + j] : 0.0;
+    }
+    if (gj_wave_regs(v, R, maxdiag)) return 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = i0 + 4 * q;
+        if (i < R && j < R) B1[i * ld + j] = v[q];
+    }
+    return 0;
+}
+
+// One wave, R <= 16, V already in registers in the gj_wave layout (lane l
+// holds column l % 16 of rows l / 16 + 4 q; zero outside R x R): writes
+// B3 = V, and B1 = V^{-1} when every pivot passes.  Returns 1 when the
+// caller has to fall back (a non-finite or non-positive diagonal, or a
+// failed pivot); B1 is then not written.  No barrier inside.
+__device__ __forceinline__ int gj_wave_from_regs(double (&v)[4], double *B1, double *B3, int R, int ld) {
+    const int l = threadIdx.x & (kWave - 1), j = l & 15, i0 = l >> 4;
+    double d = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = i0 + 4 * q;
+        if (i < R && j < R) B3[i * ld + j] = v[q];
+        if (i == j && i < R) d = v[q];
+    }
+    const int nf = !isfinite(d);
+    double mx = fabs(d);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
+    if (__any(nf) || !(mx > 0.0)) return 1;
+    if (gj_wave_regs(v, R, mx)) return 1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int i = i0 + 4 * q;
@@ -275,6 +309,31 @@ __device__ __forceinline__ int gj_block4(double *M, int R, int ld, double maxdia
     return 0;
 }
 
+// The pseudo-inverse of V = B3 into B1 by a Jacobi eigen-decomposition
+// (eigenvalues below 1e-12 of the largest dropped).  All threads of the block.
+__device__ __forceinline__ void spd_pinv(double *B1, double *B2, const double *B3, double *tmp, int R, int ld,
+                                         double *cs, int *pairs) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    int bad = 0;
+    __syncthreads();
+    for (int e = tid; e < R * ld; e += nt) B1[e] = B3[e];
+    __syncthreads();
+    jacobi_eig(B1, B2, R, ld, cs, pairs);
+    const double lmax = diag_absmax(B1, R, ld, &bad);
+    for (int i = tid; i < R; i += nt) {
+        const double l = B1[i * ld + i];
+        tmp[i] = (l > 1e-12 * lmax) ? 1.0 / l : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < R * R; e += nt) {
+        const int i = e / R, j = e - i * R;
+        double s = 0.0;
+        for (int k = 0; k < R; ++k) s += B2[i * ld + k] * tmp[k] * B2[j * ld + k];
+        B1[i * ld + j] = s;
+    }
+    __syncthreads();
+}
+
 // Scratch for spd_inverse: B1, B2, B3 (R x ld doubles each), tmp (>= R
 // doubles), cs (2*33 doubles), pairs (2*33 ints).  On entry B1 = B3 = V;
 // on exit B1 = V^{-1} (or the pseudo-inverse), B3 = V.  Returns 1 when the
@@ -298,23 +357,7 @@ __device__ __forceinline__ int spd_inverse(double *B1, double *B2, const double 
         failed = gj_block4(B1, R, ld, maxdiag);
     }
     if (!failed) return 0;
-    __syncthreads();
-    for (int e = tid; e < R * ld; e += nt) B1[e] = B3[e];
-    __syncthreads();
-    jacobi_eig(B1, B2, R, ld, cs, pairs);
-    const double lmax = diag_absmax(B1, R, ld, &bad);
-    for (int i = tid; i < R; i += nt) {
-        const double l = B1[i * ld + i];
-        tmp[i] = (l > 1e-12 * lmax) ? 1.0 / l : 0.0;
-    }
-    __syncthreads();
-    for (int e = tid; e < R * R; e += nt) {
-        const int i = e / R, j = e - i * R;
-        double s = 0.0;
-        for (int k = 0; k < R; ++k) s += B2[i * ld + k] * tmp[k] * B2[j * ld + k];
-        B1[i * ld + j] = s;
-    }
-    __syncthreads();
+    spd_pinv(B1, B2, B3, tmp, R, ld, cs, pairs);
     return 1;
 }
 
