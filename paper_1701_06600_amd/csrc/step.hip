@@ -22,6 +22,7 @@ namespace cprand {
 constexpr int kStepThreads = 512;
 constexpr int kColParts = 16;
 constexpr int kMaxParts = 8;  // partial products summed here (the gathers use at most this many chunks)
+static_assert(kColParts * kMaxRank >= kStepThreads, "tmp holds one double per thread");
 
 template <typename T>
 struct Vec16;
@@ -45,19 +46,17 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
     double *B2 = B1 + R * ld;
     double *B3 = B2 + R * ld;
     double *cs = B3 + R * ld;            // 66
-    double *tmp = cs + 66;               // max(R, kColParts * R)
+    double *tmp = cs + 66;               // kColParts * kMaxRank (>= one per thread)
     int *pairs = (int *)(tmp + kColParts * kMaxRank);  // 66
     double *Wd = (double *)(pairs + 68); // In x R: W (MIX: Re Y)
     double *Ad = Wd + (size_t)In * R;    // In x R: A (MIX: Re A-hat)
     double *Wi = Ad + (size_t)In * R;    // MIX: Im Y
     double *Ai = Wi + (size_t)In * R;    // MIX: Im A-hat
 
-    // Partial products (at most kMaxParts) are added in partial order; the
-    // loads of one element are issued together, two elements per pass.
-    for (int p = tid; p < R * R; p += kStepThreads) {
-        double v[kMaxParts];
-#pragma unroll
-        for (int c = 0; c < kMaxParts; ++c) v[c] = c < a.vparts ? a.vpart[(size_t)c * R * R + p] : 0.0;
+    // Partial products (at most kMaxParts) are added in partial order.  Gram
+    // element tid is loaded here and summed after the product loads below
+    // have been issued, so both are in flight together.
+    auto gram_sum = [&](int p, const double (&v)[kMaxParts]) {
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < kMaxParts; ++c)
@@ -65,160 +64,217 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
         const int i = p / R, j = p - i * R;
         B1[i * ld + j] = acc;
         B3[i * ld + j] = acc;
+    };
+    // R <= 16: wave 0 loads V in the register layout of the one-wave
+    // Gauss-Jordan inverse and inverts it while the other waves load and sum
+    // the product partials; larger R: Gram element tid is loaded here and
+    // summed after the product loads have been issued.
+    const bool wave_inv = R <= 16;
+    __shared__ int s_failed;
+    double vv[kMaxParts];
+    if (!wave_inv) {
+#pragma unroll
+        for (int c = 0; c < kMaxParts; ++c)
+            vv[c] = (tid < R * R && c < a.vparts) ? a.vpart[(size_t)c * R * R + tid] : 0.0;
     }
-    constexpr int VL = 16 / sizeof(T);  // values per 16-byte load
-    typedef typename Vec16<T>::type V16;
-    if (!a.mix && a.wsi == 1 && In % VL == 0 && a.wsr % VL == 0 && a.wps % VL == 0) {
-        // (i .. i+VL-1, r) of every partial in one 16-byte load each
-        const T *w = (const T *)a.W;
-        const int ng = R * (In / VL);
-        for (int g = tid; g < ng; g += kStepThreads) {
-            const int r = g / (In / VL), i0 = (g - r * (In / VL)) * VL;
-            V16 v[kMaxParts];
-#pragma unroll
-            for (int p = 0; p < kMaxParts; ++p)
-                v[p] = p < a.wparts ? *(const V16 *)(w + (int64_t)p * a.wps + (int64_t)r * a.wsr + i0) : V16{};
-#pragma unroll
-            for (int u = 0; u < VL; ++u) {
-                double acc = 0.0;
-#pragma unroll
+    // The product partials: all threads, or (R <= 16) waves 1.. while wave 0
+    // loads and inverts V.
+    const int yt = wave_inv ? tid - kWave : tid, ys = wave_inv ? kStepThreads - kWave : kStepThreads;
+    if (yt >= 0) {
+        constexpr int VL = 16 / sizeof(T);  // values per 16-byte load
+        typedef typename Vec16<T>::type V16;
+        if (!a.mix && a.wsi == 1 && In % VL == 0 && a.wsr % VL == 0 && a.wps % VL == 0) {
+            // (i .. i+VL-1, r) of every partial in one 16-byte load each
+            const T *w = (const T *)a.W;
+            const int ng = R * (In / VL);
+            for (int g = yt; g < ng; g += ys) {
+                const int r = g / (In / VL), i0 = (g - r * (In / VL)) * VL;
+                V16 v[kMaxParts];
+    #pragma unroll
                 for (int p = 0; p < kMaxParts; ++p)
-                    if (p < a.wparts) acc += (double)vget(v[p], u);
-                Wd[(i0 + u) * R + r] = acc;
+                    v[p] = p < a.wparts ? *(const V16 *)(w + (int64_t)p * a.wps + (int64_t)r * a.wsr + i0) : V16{};
+    #pragma unroll
+                for (int u = 0; u < VL; ++u) {
+                    double acc = 0.0;
+    #pragma unroll
+                    for (int p = 0; p < kMaxParts; ++p)
+                        if (p < a.wparts) acc += (double)vget(v[p], u);
+                    Wd[(i0 + u) * R + r] = acc;
+                }
             }
-        }
-    } else if (a.mix && In % VL == 0) {
-        // real and imaginary rows of column c, VL consecutive l per load
-        const T *y = (const T *)a.W;
-        const size_t cstride = (size_t)2 * R * In;
-        const int ng = R * (In / VL);
-        for (int g = tid; g < ng; g += kStepThreads) {
-            const int c = g / (In / VL), l0 = (g - c * (In / VL)) * VL;
-            V16 vr[kMaxParts], vi[kMaxParts];
-#pragma unroll
-            for (int p = 0; p < kMaxParts; ++p) {
-                vr[p] = p < a.wparts ? *(const V16 *)(y + p * cstride + (size_t)c * In + l0) : V16{};
-                vi[p] = p < a.wparts ? *(const V16 *)(y + p * cstride + (size_t)(R + c) * In + l0) : V16{};
-            }
-#pragma unroll
-            for (int u = 0; u < VL; ++u) {
-                double re = 0.0, im = 0.0;
-#pragma unroll
-                for (int p = 0; p < kMaxParts; ++p)
-                    if (p < a.wparts) {
-                        re += (double)vget(vr[p], u);
-                        im += (double)vget(vi[p], u);
+        } else if (a.mix && In % VL == 0) {
+            // real and imaginary rows of column c, VL consecutive l per load; two
+            // groups per thread per pass, all their loads in flight together
+            const T *y = (const T *)a.W;
+            const size_t cstride = (size_t)2 * R * In;
+            const int ng = R * (In / VL);
+            for (int g0 = yt; g0 < ng; g0 += 2 * ys) {
+                V16 vr[2][kMaxParts], vi[2][kMaxParts];
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int g = g0 + h * ys;
+                    const int c = g / (In / VL), l0 = (g - c * (In / VL)) * VL;
+    #pragma unroll
+                    for (int p = 0; p < kMaxParts; ++p) {
+                        const bool ok = g < ng && p < a.wparts;
+                        vr[h][p] = ok ? *(const V16 *)(y + p * cstride + (size_t)c * In + l0) : V16{};
+                        vi[h][p] = ok ? *(const V16 *)(y + p * cstride + (size_t)(R + c) * In + l0) : V16{};
                     }
-                Wd[(l0 + u) * R + c] = re;
-                Wi[(l0 + u) * R + c] = im;
+                }
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int g = g0 + h * ys;
+                    if (g >= ng) continue;
+                    const int c = g / (In / VL), l0 = (g - c * (In / VL)) * VL;
+    #pragma unroll
+                    for (int u = 0; u < VL; ++u) {
+                        double re = 0.0, im = 0.0;
+    #pragma unroll
+                        for (int p = 0; p < kMaxParts; ++p)
+                            if (p < a.wparts) {
+                                re += (double)vget(vr[h][p], u);
+                                im += (double)vget(vi[h][p], u);
+                            }
+                        Wd[(l0 + u) * R + c] = re;
+                        Wi[(l0 + u) * R + c] = im;
+                    }
+                }
+            }
+        } else if (!a.mix) {
+            const T *w = (const T *)a.W;
+            for (int e0 = yt; e0 < In * R; e0 += 2 * ys) {
+                T v[2][kMaxParts];
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int e = e0 + h * ys;
+                    const int i = e / R, r = e - i * R;
+    #pragma unroll
+                    for (int p = 0; p < kMaxParts; ++p)
+                        v[h][p] = (e < In * R && p < a.wparts) ? w[(int64_t)p * a.wps + (int64_t)i * a.wsi + (int64_t)r * a.wsr]
+                                                              : (T)0;
+                }
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int e = e0 + h * ys;
+                    double acc = 0.0;
+    #pragma unroll
+                    for (int p = 0; p < kMaxParts; ++p)
+                        if (p < a.wparts) acc += (double)v[h][p];
+                    if (e < In * R) Wd[e] = acc;
+                }
+            }
+        } else {
+            const T *y = (const T *)a.W;
+            const size_t cstride = (size_t)2 * R * In;
+            for (int e0 = yt; e0 < In * R; e0 += 2 * ys) {
+                T vr[2][kMaxParts], vi[2][kMaxParts];
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int e = e0 + h * ys;
+                    const int c = e / In, l = e - c * In;
+                    const bool ok = e < In * R;
+    #pragma unroll
+                    for (int p = 0; p < kMaxParts; ++p) {
+                        vr[h][p] = (ok && p < a.wparts) ? y[p * cstride + (size_t)c * In + l] : (T)0;
+                        vi[h][p] = (ok && p < a.wparts) ? y[p * cstride + (size_t)(R + c) * In + l] : (T)0;
+                    }
+                }
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int e = e0 + h * ys;
+                    const int c = e / In, l = e - c * In;
+                    double re = 0.0, im = 0.0;
+    #pragma unroll
+                    for (int p = 0; p < kMaxParts; ++p)
+                        if (p < a.wparts) {
+                            re += (double)vr[h][p];
+                            im += (double)vi[h][p];
+                        }
+                    if (e < In * R) {
+                        Wd[l * R + c] = re;
+                        Wi[l * R + c] = im;
+                    }
+                }
             }
         }
-    } else if (!a.mix) {
-        const T *w = (const T *)a.W;
-        for (int e0 = tid; e0 < In * R; e0 += 2 * kStepThreads) {
-            T v[2][kMaxParts];
+    }
+    int failed;
+    if (wave_inv) {
+        if (tid < kWave) {  // the whole of wave 0
+            const int j = tid & 15, i0 = tid >> 4;
+            double v[4], vq[4][kMaxParts];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int e = e0 + h * kStepThreads;
-                const int i = e / R, r = e - i * R;
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + 4 * q;
+                const bool in = i < R && j < R;
+                const int e = in ? i * R + j : 0;
 #pragma unroll
-                for (int p = 0; p < kMaxParts; ++p)
-                    v[h][p] = (e < In * R && p < a.wparts) ? w[(int64_t)p * a.wps + (int64_t)i * a.wsi + (int64_t)r * a.wsr]
-                                                          : (T)0;
-            }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int e = e0 + h * kStepThreads;
+                for (int c = 0; c < kMaxParts; ++c) {
+                    const int cc = c < a.vparts ? c : 0;
+                    vq[q][c] = a.vpart[(size_t)cc * R * R + e];
+                }
                 double acc = 0.0;
 #pragma unroll
-                for (int p = 0; p < kMaxParts; ++p)
-                    if (p < a.wparts) acc += (double)v[h][p];
-                if (e < In * R) Wd[e] = acc;
+                for (int c = 0; c < kMaxParts; ++c)
+                    if (c < a.vparts) acc += vq[q][c];
+                v[q] = in ? acc : 0.0;
             }
+            const int f = gj_wave_from_regs(v, B1, B3, R, ld);
+            if (tid == 0) s_failed = f;
         }
+        __syncthreads();
+        failed = s_failed;
+        if (failed) spd_pinv(B1, B2, B3, tmp, R, ld, cs, pairs);
     } else {
-        const T *y = (const T *)a.W;
-        const size_t cstride = (size_t)2 * R * In;
-        for (int e0 = tid; e0 < In * R; e0 += 2 * kStepThreads) {
-            T vr[2][kMaxParts], vi[2][kMaxParts];
+        if (tid < R * R) gram_sum(tid, vv);
+        for (int p = tid + kStepThreads; p < R * R; p += kStepThreads) {
+            double v[kMaxParts];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int e = e0 + h * kStepThreads;
-                const int c = e / In, l = e - c * In;
-                const bool ok = e < In * R;
-#pragma unroll
-                for (int p = 0; p < kMaxParts; ++p) {
-                    vr[h][p] = (ok && p < a.wparts) ? y[p * cstride + (size_t)c * In + l] : (T)0;
-                    vi[h][p] = (ok && p < a.wparts) ? y[p * cstride + (size_t)(R + c) * In + l] : (T)0;
-                }
-            }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int e = e0 + h * kStepThreads;
-                const int c = e / In, l = e - c * In;
-                double re = 0.0, im = 0.0;
-#pragma unroll
-                for (int p = 0; p < kMaxParts; ++p)
-                    if (p < a.wparts) {
-                        re += (double)vr[h][p];
-                        im += (double)vi[h][p];
-                    }
-                if (e < In * R) {
-                    Wd[l * R + c] = re;
-                    Wi[l * R + c] = im;
-                }
-            }
+            for (int c = 0; c < kMaxParts; ++c) v[c] = c < a.vparts ? a.vpart[(size_t)c * R * R + p] : 0.0;
+            gram_sum(p, v);
         }
+        __syncthreads();
+        failed = spd_inverse(B1, B2, B3, tmp, R, ld, cs, pairs);
     }
-    __syncthreads();
-    const int failed = spd_inverse(B1, B2, B3, tmp, R, ld, cs, pairs);
     if (tid == 0 && a.info && failed) *a.info = CPRAND_W_PINV;
     if (a.mix) {
-        // Y_s = (Y + P conj Y) / 2 in place: rows k and I_n - k form a pair
-        // (rows 0 and I_n / 2 pair with themselves), one thread per pair
+        // A-hat (unnormalised) = Y_s V^{-1} with Y_s = (Y + P conj Y) / 2:
+        // rows k and I_n - k of Y_s are conjugates (rows 0 and I_n / 2 pair
+        // with themselves), so one thread takes the pair, reads both rows of
+        // Y and writes both rows of A-hat.  Thread t keeps rank r = t mod R
+        // and rows t / R, t / R + kstride, ..., and sums |A-hat|^2 of its
+        // rows; the column norms are then closed in a fixed order.
         const int half = In / 2 + 1;
-        for (int e = tid; e < half * R; e += kStepThreads) {
-            const int k = e / R, r = e - k * R;
-            const int kk = k == 0 ? 0 : In - k;
-            const double yr = Wd[k * R + r], yi = Wi[k * R + r];
-            const double zr = Wd[kk * R + r], zi = Wi[kk * R + r];
-            const double sr = 0.5 * (yr + zr), si = 0.5 * (yi - zi);
-            Wd[k * R + r] = sr;
-            Wi[k * R + r] = si;
-            if (kk != k) {
-                Wd[kk * R + r] = sr;
-                Wi[kk * R + r] = -si;
+        const int kstride = kStepThreads / R;
+        double nsq = 0.0;
+        if (tid < kstride * R) {
+            const int r = tid % R;
+            for (int k = tid / R; k < half; k += kstride) {
+                const int kk = k == 0 ? 0 : In - k;
+                double sr = 0.0, si = 0.0;
+                for (int j = 0; j < R; ++j) {
+                    const double h = B1[j * ld + r];
+                    sr += (Wd[k * R + j] + Wd[kk * R + j]) * h;
+                    si += (Wi[k * R + j] - Wi[kk * R + j]) * h;
+                }
+                sr *= 0.5;
+                si *= 0.5;
+                Ad[k * R + r] = sr;
+                Ai[k * R + r] = si;
+                const double q2 = sr * sr + si * si;
+                nsq += q2;
+                if (kk != k) {
+                    Ad[kk * R + r] = sr;
+                    Ai[kk * R + r] = -si;
+                    nsq += q2;
+                }
             }
         }
-        __syncthreads();
-        // A-hat (unnormalised) = Y_s V^{-1}; row I_n - k is the conjugate of row k
-        for (int e = tid; e < half * R; e += kStepThreads) {
-            const int k = e / R, r = e - k * R;
-            const int kk = k == 0 ? 0 : In - k;
-            double sr = 0.0, si = 0.0;
-            for (int j = 0; j < R; ++j) {
-                const double h = B1[j * ld + r];
-                sr += Wd[k * R + j] * h;
-                si += Wi[k * R + j] * h;
-            }
-            Ad[k * R + r] = sr;
-            Ai[k * R + r] = si;
-            if (kk != k) {
-                Ad[kk * R + r] = sr;
-                Ai[kk * R + r] = -si;
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < kColParts * R; e += kStepThreads) {
-            const int r = e / kColParts, part = e - r * kColParts;
-            double s = 0.0;
-            for (int i = part; i < In; i += kColParts) s += Ad[i * R + r] * Ad[i * R + r] + Ai[i * R + r] * Ai[i * R + r];
-            tmp[r * kColParts + part] = s;
-        }
+        tmp[tid] = nsq;
         __syncthreads();
         if (tid < R) {
             double s = 0.0;
-            for (int part = 0; part < kColParts; ++part) s += tmp[tid * kColParts + part];
+            for (int k0 = 0; k0 < kstride; ++k0) s += tmp[k0 * R + tid];
             const double l = sqrt(s);
             B2[tid] = l;
             a.lambda[tid] = l;
