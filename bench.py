@@ -39,11 +39,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the mixing pass on the 400^3 workload (average of
-# the three passes), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of
-# bench.py --legs mixonly, scaled by what the same counters read for a 1 GiB
-# device copy (FETCH_SIZE x 2, WRITE_SIZE x 1).  Valid for the kernel as
-# measured; set to None when the mixing kernel changes until re-measured.
-MIX_TRAFFIC_BYTES = (2 * 125158 + 500052 + 2 * (2 * 250105 + 500000)) * 1024 / 3
+# the three passes of the main leg, the last one also writing its mode-major
+# copy), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, scaled by what the
+# same counters read for a 1 GiB device copy (FETCH_SIZE x 2, WRITE_SIZE x 1).
+# Valid for the kernel as measured; None when the mixing kernel has changed
+# since the counters were taken.
+MIX_TRAFFIC_BYTES = None
 # the same 1 GiB copy (read + write) took 423 us: 5.08 TB/s, the practical ceiling seen
 COPY_GBPS = 2 * 1073741824 / 423e-6 / 1e9
 
@@ -55,6 +56,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--layout", type=int, default=0, help="0: mode-major copies of X-hat, 1: strided gathers")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="main leg: 0 direct launches (fit estimate on its own stream), 1 one HIP graph per iteration")
     ap.add_argument("--legs", default="main,precision,learned")
     ap.add_argument("--train-instances", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -102,7 +105,7 @@ def main():
     def opts(mix):
         return P.make_opts(R, S, P_hat=w.P_hat, max_iters=w.max_iters, seed=w.seed, tol=w.tol,
                            fit_target=w.fit_target, mix=P.MIX_FFT if mix else P.MIX_NONE,
-                           layout=args.layout, use_graph=1)
+                           layout=args.layout, use_graph=args.graph)
 
     plan = P.Plan(Xv, opts(True))
 
@@ -129,7 +132,9 @@ def main():
     # dominant kernel: the mixing pass (HIP events around each pass, in the timed steps)
     P_el = math.prod(w.dims)
     mix_ms = [sum(r["mix_ms"][m] for r in runs) / len(runs) for m in range(3)]
-    mix_bytes = [P_el * (4 + 8)] + [P_el * 16] * 2       # pass 0 reads FP32, writes complex64
+    # pass 0 reads FP32 and writes complex64; the last pass also writes its
+    # mode-major copy when the plan folded that copy into it
+    mix_bytes = [P_el * (4 + 8), P_el * 16, P_el * (24 if runs[-1]["fused"] & 2 else 16)]
     mix_launch_ms = sum(mix_ms) / 3
     mix_achieved = sum(mix_bytes) / 3 / (mix_launch_ms * 1e-3) / 1e9
 
@@ -176,6 +181,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        "launch": "HIP graph per iteration" if args.graph else "direct launches, fit estimate on a second stream",
         "config": {"workload": "CPRAND-MIX, 400x400x400 FP32, R=10, congruence 0.5, 1% noise, "
                                "S=300, P-hat=2^14, paper stop rule",
                    "layout": "strided X-hat gathers" if args.layout else "mode-major X-hat copies"},

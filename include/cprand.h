@@ -303,7 +303,9 @@ typedef struct cprand_report {
     int32_t *proposal_history; /* host, max_iters entries (proposal in use), or NULL */
     double norm_ms;                      /* ||X|| pass (HIP events) */
     double mix_ms[CPRAND_MAX_ORDER];     /* mixing pass along each mode, 0 when not mixed */
-    double layout_ms[CPRAND_MAX_ORDER];  /* mode-major copy for each mode, 0 when none */
+    double layout_ms[CPRAND_MAX_ORDER];  /* mode-major copy for each mode, 0 when none or fused */
+    int32_t fused;          /* setup work folded into the mixing passes: bit 0, ||X|| in the first
+                               pass; bit 1, the last mode's mode-major copy written by the last pass */
 } cprand_report;
 
 typedef struct cprand_plan cprand_plan;

@@ -331,7 +331,7 @@ class Plan:
         return {"status": rc, "lambda": lam, "iters": rep.iters, "flags": rep.flags, "fit_est": rep.fit_est,
                 "setup_ms": rep.setup_ms, "loop_ms": rep.loop_ms, "norm_ms": rep.norm_ms,
                 "mix_ms": [rep.mix_ms[i] for i in range(order)],
-                "layout_ms": [rep.layout_ms[i] for i in range(order)],
+                "layout_ms": [rep.layout_ms[i] for i in range(order)], "fused": rep.fused,
                 "fit_history": [hist[i] for i in range(rep.iters)],
                 "proposal_history": [props[i] for i in range(rep.iters)]}
 

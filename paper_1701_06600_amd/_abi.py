@@ -43,7 +43,7 @@ class cprand_report(C.Structure):
                 ("fit_history", C.POINTER(C.c_double)),
                 ("proposal_history", C.POINTER(C.c_int32)),
                 ("norm_ms", C.c_double), ("mix_ms", C.c_double * MAX_ORDER),
-                ("layout_ms", C.c_double * MAX_ORDER)]
+                ("layout_ms", C.c_double * MAX_ORDER), ("fused", C.c_int32)]
 
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcprand.so")

@@ -107,6 +107,8 @@ struct cprand_plan {
     double *snap_lambda[3] = {};
     std::vector<void *> allocs;
     hipStream_t cap = nullptr;
+    hipStream_t fst = nullptr;       // the fit estimates of the direct-launch loop
+    hipEvent_t ev_state[2] = {};     // iteration state complete (parity of t)
     hipEvent_t ev[4] = {};
     // setup timing: [0,1] norm, [2+2m, 3+2m] mix pass m, [2+2N+2m, 3+2N+2m] layout copy m
     hipEvent_t tev[2 + 4 * CPRAND_MAX_ORDER] = {};
@@ -114,6 +116,9 @@ struct cprand_plan {
         for (void *p : allocs) (void)hipFree(p);
         if (hist_host) (void)hipHostFree(hist_host);
         if (cap) (void)hipStreamDestroy(cap);
+        if (fst) (void)hipStreamDestroy(fst);
+        for (auto &e : ev_state)
+            if (e) (void)hipEventDestroy(e);
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
         for (auto &e : tev)
@@ -211,9 +216,30 @@ FitArgs fit_args(const cprand_plan *p, const void *xdata) {
 }
 
 // One outer iteration on `st`.
-hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CPRAND_MAX_ORDER], hipStream_t st) {
+// Direct launches of a non-adaptive loop: iteration t passed by value; the
+// steps also write the factors and lambda into snapshot buffer t mod 2, and
+// the fit estimate of iteration t runs on fit_st from that copy, so the next
+// iteration's gathers need not wait for it.
+struct IterCtl {
+    uint64_t t;
+    hipStream_t fit_st;
+    hipEvent_t ev_state;
+};
+
+// Segment m of snapshot buffer b: the factors (A-hat under mixing) in order,
+// then lambda.
+static char *snap_segment(const cprand_plan *p, int b, int m) {
+    const size_t tsz = p->dbl ? 8 : 4;
+    size_t off = 0;
+    for (int k = 0; k < m; ++k) off += (size_t)p->dims[k] * p->o.R * tsz * (p->mix ? 2 : 1);
+    return (char *)p->snapbuf[b] + off;
+}
+
+hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CPRAND_MAX_ORDER], hipStream_t st,
+                             const IterCtl *ic = nullptr) {
     hipError_t e = hipSuccess;
     const int N = p->N, R = p->o.R;
+    const int sb = ic ? (int)(ic->t & 1) : 0;
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         const View &v = p->gview[n];
         const void *vd = view_ptr(p, v, xdata);
@@ -268,7 +294,12 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
             ga.cdf = &cdf;
         }
         ga.seed = p->o.seed;
-        ga.t_dev = p->t_dev;
+        if (ic) {
+            ga.t = ic->t;
+            ga.t_dev = nullptr;
+        } else {
+            ga.t_dev = p->t_dev;
+        }
         ga.wpart = p->wpart;
         ga.vpart = p->vpart;
         e = launch_gather(gp, ga, st);
@@ -307,6 +338,10 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
             sa.Ahat = p->mix ? p->fhat[n] : nullptr;
             sa.lambda = p->lambda;
             sa.info = p->info;
+            if (ic) {
+                sa.snapA = snap_segment(p, sb, n);
+                sa.snap_lambda = (double *)snap_segment(p, sb, N);
+            }
             e = launch_step_finish(sa, p->dbl, st);
             continue;
         }
@@ -366,11 +401,29 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
             if (fp) e = launch_factor_mix(fp, p->dbl, (int32_t)In, R, p->fac[n], p->signs + p->seg_off[n], p->fhat[n],
                                           false, st);
         }
+        if (e == hipSuccess && ic) {
+            const size_t b = (size_t)In * R * (p->dbl ? 8 : 4) * (p->mix ? 2 : 1);
+            e = hipMemcpyAsync(snap_segment(p, sb, n), p->mix ? p->fhat[n] : p->fac[n], b, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(snap_segment(p, sb, N), p->lambda, (size_t)R * 8, hipMemcpyDeviceToDevice, st);
+        }
     }
     if (e != hipSuccess) return e;
     FitArgs fa = fit_args(p, xdata);
     fa.frow = p->frow;
     fa.fx = p->fx;
+    if (ic) {
+        // iteration t's state is in snapshot buffer t mod 2: estimate from it on the fit stream
+        for (int m = 0; m < N; ++m) fa.A.p[m] = snap_segment(p, sb, m);
+        fa.lambda = (const double *)snap_segment(p, sb, N);
+        fa.t_dev = nullptr;
+        fa.t = ic->t;
+        e = hipEventRecord(ic->ev_state, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ic->fit_st, ic->ev_state, 0);
+        int32_t nb = 0;
+        if (e == hipSuccess) e = launch_fit_partial(fa, &nb, ic->fit_st);
+        return e;
+    }
     if (!p->adaptive) {
         const size_t tsz = p->dbl ? 8 : 4;
         for (int m = 0; m < N; ++m) {  // under mixing the state is A-hat (A is formed at the end)
@@ -581,6 +634,8 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
         e = hipHostMalloc((void **)&p->hist_host, (size_t)o.max_iters * 8, hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&p->hist_mapped, p->hist_host, 0);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->fst, hipStreamNonBlocking);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&p->ev_state[i], hipEventDisableTiming);
     for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&p->ev[i]);
     for (int i = 0; i < 2 + 4 * CPRAND_MAX_ORDER && e == hipSuccess; ++i) e = hipEventCreate(&p->tev[i]);
     if (e != hipSuccess) {
@@ -778,11 +833,22 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
     std::vector<int> levels;
     if (!p->adaptive) {
         // One iteration ahead: iteration t+1 is launched before the host reads
-        // F-hat of iteration t; every iteration ends by saving the factors and
-        // lambda (buffer t mod 2), so a stop at t restores exactly that state.
+        // F-hat of iteration t; every iteration saves the factors and lambda
+        // (buffer t mod 2), so a stop at t restores exactly that state.  With
+        // direct launches the fit estimate of t runs on its own stream from
+        // that copy while iteration t+1 proceeds; snapshot buffer t mod 2 is
+        // written again only by iteration t+2, launched after the host has
+        // waited for the fit of t.
         auto launch_one = [&](int t) {
-            hipError_t r = exec ? hipGraphLaunch(exec, st) : enqueue_iteration(p, X->data, contig_x, st);
-            if (r == hipSuccess) r = hipEventRecord(p->ev[t & 1 ? 3 : 2], st);
+            hipError_t r;
+            if (exec) {
+                r = hipGraphLaunch(exec, st);
+                if (r == hipSuccess) r = hipEventRecord(p->ev[t & 1 ? 3 : 2], st);
+            } else {
+                const IterCtl ic{(uint64_t)t, p->fst, p->ev_state[t & 1]};
+                r = enqueue_iteration(p, X->data, contig_x, st, &ic);
+                if (r == hipSuccess) r = hipEventRecord(p->ev[t & 1 ? 3 : 2], p->fst);
+            }
             return r;
         };
         bool ahead = false;
@@ -805,6 +871,7 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
             ahead = false;
         }
         if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->fst);
         if (e == hipSuccess && ahead) {  // undo the iteration launched past the stop
             const char *sb = (const char *)p->snapbuf[(it - 1) & 1];
             const size_t tsz = p->dbl ? 8 : 4;
@@ -904,6 +971,7 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
         rep->loop_ms = ms;
         (void)hipEventElapsedTime(&ms, tev[0], tev[1]);
         rep->norm_ms = ms;
+        rep->fused = (p->mix && norm_done ? 1 : 0) | (copied_last ? 2 : 0);
         for (int m = 0; m < CPRAND_MAX_ORDER; ++m) {
             rep->mix_ms[m] = 0.0;
             rep->layout_ms[m] = 0.0;

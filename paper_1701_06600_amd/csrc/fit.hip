@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_partial_kernel(FitArgs a) {
         tot = block_sum<kFitThreads>(tot, sh);
         if (tid == 0) {
             const double f = 1.0 - sqrt(a.P * (tot / (double)a.P_hat)) / *a.normX;
-            const uint64_t t = a.t_dev ? *a.t_dev : 0;
+            const uint64_t t = a.t_dev ? *a.t_dev : a.t;
             if (a.fit_out) *a.fit_out = f;
             if (a.hist) a.hist[t] = f;
             if (a.hist_host) a.hist_host[t] = f;

@@ -137,6 +137,8 @@ struct StepArgs {
     void *A;                // row-major In x R, real type (not written under mixing)
     void *Ahat;             // MIX: row-major In x R complex
     double *lambda;
+    void *snapA;            // optional second copy of the factor written (A, or A-hat under mixing)
+    double *snap_lambda;    // optional second copy of lambda
     int32_t *info;          // set to CPRAND_W_PINV when the pseudo-inverse was used
 };
 size_t step_finish_lds(int32_t In, int32_t R, bool mix);
@@ -180,6 +182,7 @@ struct FitArgs {
     double *hist;
     double *hist_host;
     uint64_t *t_dev;
+    uint64_t t;           // the iteration when t_dev is NULL
     // Optional cached fit set (the same P-hat entries are used at every
     // iteration): rows [P_hat][order] and tensor values [P_hat][2] (re, im)
     // written once by launch_fit_set; when NULL the entries are regenerated

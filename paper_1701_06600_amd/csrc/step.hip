@@ -278,14 +278,20 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
             const double l = sqrt(s);
             B2[tid] = l;
             a.lambda[tid] = l;
+            if (a.snap_lambda) a.snap_lambda[tid] = l;
         }
         __syncthreads();
         T *Ah = (T *)a.Ahat;
         for (int e = tid; e < In * R; e += kStepThreads) {
             const double l = B2[e % R];
             const double q = l > 0.0 ? 1.0 / l : 1.0;
-            Ah[2 * (size_t)e] = (T)(Ad[e] * q);
-            Ah[2 * (size_t)e + 1] = (T)(Ai[e] * q);
+            const T re = (T)(Ad[e] * q), im = (T)(Ai[e] * q);
+            Ah[2 * (size_t)e] = re;
+            Ah[2 * (size_t)e + 1] = im;
+            if (a.snapA) {
+                ((T *)a.snapA)[2 * (size_t)e] = re;
+                ((T *)a.snapA)[2 * (size_t)e + 1] = im;
+            }
         }
         return;
     }
@@ -336,6 +342,7 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
         const double l = sqrt(s);
         B2[tid] = l;  // B2 is free after the inversion
         a.lambda[tid] = l;
+        if (a.snap_lambda) a.snap_lambda[tid] = l;
     }
     __syncthreads();
     T *A = (T *)a.A;
@@ -343,7 +350,9 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
         const int r = e % R;
         const double l = B2[r];
         const T v = (T)Ad[e];
-        A[e] = l > 0.0 ? (T)((double)v / l) : v;
+        const T nv = l > 0.0 ? (T)((double)v / l) : v;
+        A[e] = nv;
+        if (a.snapA) ((T *)a.snapA)[e] = nv;
     }
 }
 

@@ -124,3 +124,28 @@ def test_plan_validation():
     assert P._lib.cprand_plan_create(C.byref(Xd), C.byref(o), C.byref(h)) == P.EINVAL
     o = P.make_opts(R=4, S=10, proposal=P.PROPOSAL_TABLE)
     assert P._lib.cprand_plan_create(C.byref(X), C.byref(o), C.byref(h)) == P.EINVAL
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes structures of the binding have the sizes and field offsets
+    that a C compiler gives the structures of include/cprand.h."""
+    structs = [_abi.cprand_tensor, _abi.cprand_opts, _abi.cprand_report]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "cprand.h"', "int main(void) {"]
+    for st in structs:
+        n = st.__name__
+        lines.append('    printf("%s sizeof %%zu\\n", sizeof(%s));' % (n, n))
+        for f in st._fields_:
+            lines.append('    printf("%s %s %%zu\\n", offsetof(%s, %s));' % (n, f[0], n, f[0]))
+    lines.append("    return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {(l.split()[0], l.split()[1]): int(l.split()[2]) for l in out if l.strip()}
+    for st in structs:
+        n = st.__name__
+        assert got[(n, "sizeof")] == C.sizeof(st), n
+        for f in st._fields_:
+            assert got[(n, f[0])] == getattr(st, f[0]).offset, (n, f[0])

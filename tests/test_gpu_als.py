@@ -41,12 +41,16 @@ def test_cprand_50cube_f64_tracks_oracle(use_graph):
         assert np.allclose(a, b, atol=1e-7)
 
 
-def test_cprand_f32_stop_rules_and_fit():
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_cprand_f32_stop_rules_and_fit(use_graph):
+    """Stops before max_iters, so the iteration launched past the stop is
+    undone from the saved state (graph: saved by the fit kernel; direct
+    launches: saved by the step kernels, fit estimated on its own stream)."""
     p = synth.make_problem((80, 70, 60), 5, congruence=0.5, noise=0.01, seed=21)
     X = synth.dense_tensor(p).astype(np.float32).astype(np.float64)
     S = OC.sample_size(5)
     out, A = _run_gpu(X, p.init, 5, S, 1234, torch.float32, max_iters=200, tol=1e-4,
-                      fit_target=1 - 1.2 * 0.01)
+                      fit_target=1 - 1.2 * 0.01, use_graph=use_graph)
     lam_r, A_r, hist_r = OC.cprand(X, 5, S, p.init, 1234, 200, tol=1e-4, fit_target=1 - 1.2 * 0.01)
     F = OC.exact_fit(X, out["lambda"].cpu().numpy(), A)
     assert abs(F - OC.exact_fit(X, lam_r, A_r)) < 1e-3
@@ -56,7 +60,7 @@ def test_cprand_f32_stop_rules_and_fit():
     sc, sc_r = OS.score(p.factors, A), OS.score(p.factors, A_r)
     assert abs(sc - sc_r) < 1e-3, (sc, sc_r)
     # without the change-in-fit rule the run recovers the factors
-    out, A = _run_gpu(X, p.init, 5, S, 1234, torch.float32, max_iters=200)
+    out, A = _run_gpu(X, p.init, 5, S, 1234, torch.float32, max_iters=200, use_graph=use_graph)
     F = OC.exact_fit(X, out["lambda"].cpu().numpy(), A)
     sc = OS.score(p.factors, A)
     assert abs(F - 0.99) < 2e-3 and sc > 0.99, (F, sc)
@@ -72,10 +76,11 @@ def test_cprand_mix_f32_on_coherent_tensor():
     assert abs(out["fit_history"][-1] - hist_r[-1]) < 1e-3
 
 
-def test_cprand_mix_f64_tracks_oracle():
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_cprand_mix_f64_tracks_oracle(use_graph):
     p = synth.make_problem((20, 30, 12), 4, congruence=0.5, noise=0.01, seed=8)
     X = synth.dense_tensor(p)
-    out, A = _run_gpu(X, p.init, 4, 60, 9, torch.float64, max_iters=30, mix=P.MIX_FFT)
+    out, A = _run_gpu(X, p.init, 4, 60, 9, torch.float64, max_iters=30, mix=P.MIX_FFT, use_graph=use_graph)
     lam_r, A_r, hist_r = OC.cprand_mix(X, 4, 60, p.init, 9, 30)
     assert np.max(np.abs(np.array(out["fit_history"]) - np.array(hist_r))) < 1e-8
     for a, b in zip(A, A_r):

@@ -96,14 +96,16 @@ def test_fullsize_fit_estimate_matches_oracle(big):
     assert abs(F - ref) < 1e-6, (F, ref)
 
 
-def test_fullsize_decomposition_tracks_oracle(big):
-    """The benchmarked decomposition (CPRAND-MIX, mode-major X-hat copies, one
-    HIP graph per iteration, one-iteration run-ahead) against the oracle's
-    CPRAND-MIX for its first iterations: F-hat history within 1e-3."""
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_fullsize_decomposition_tracks_oracle(big, use_graph):
+    """The benchmarked decomposition (CPRAND-MIX, mode-major X-hat copies,
+    one-iteration run-ahead; direct launches with the fit estimate on its own
+    stream, or one HIP graph per iteration) against the oracle's CPRAND-MIX
+    for its first iterations: F-hat history within 1e-3."""
     iters = 3
     A = factors_dev(big["init"])
     opts = P.make_opts(W.R, W.S, P_hat=W.P_hat, max_iters=iters, seed=W.seed, tol=0.0, mix=P.MIX_FFT,
-                       layout=0, use_graph=1)
+                       layout=0, use_graph=use_graph)
     out = P.cprand_als(big["Xv"], A, opts)
     _, _, hist = OC.cprand_mix(big["host"], W.R, W.S, big["init"], W.seed, iters, P_hat=W.P_hat)
     got = np.array(out["fit_history"])
