@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 # same counters read for a 1 GiB device copy (FETCH_SIZE x 2, WRITE_SIZE x 1).
 # Valid for the kernel as measured; None when the mixing kernel has changed
 # since the counters were taken.
-MIX_TRAFFIC_BYTES = None
+MIX_TRAFFIC_BYTES = (2 * 125177 + 500016 + 2 * 250169.5 + 500000 + 2 * 250122.5 + 1000000) * 1024 / 3
 # the same 1 GiB copy (read + write) took 423 us: 5.08 TB/s, the practical ceiling seen
 COPY_GBPS = 2 * 1073741824 / 423e-6 / 1e9
 
@@ -102,10 +102,20 @@ def main():
         print(json.dumps({"mixonly": True, "dims": list(w.dims)}), flush=True)
         return
 
-    def opts(mix):
-        return P.make_opts(R, S, P_hat=w.P_hat, max_iters=w.max_iters, seed=w.seed, tol=w.tol,
+    def opts(mix, max_iters=w.max_iters):
+        return P.make_opts(R, S, P_hat=w.P_hat, max_iters=max_iters, seed=w.seed, tol=w.tol,
                            fit_target=w.fit_target, mix=P.MIX_FFT if mix else P.MIX_NONE,
                            layout=args.layout, use_graph=args.graph)
+
+    if "mixplan" in legs:
+        # the plan's setup (mixing passes with the folded norm and mode-major
+        # copy) and one iteration, twice (for hardware counters of the passes)
+        plan = P.Plan(Xv, opts(True, max_iters=1))
+        for _ in range(2):
+            r = plan.run(Xv, [M.clone() for M in init])
+        torch.cuda.synchronize()
+        print(json.dumps({"mixplan": True, "fused": r["fused"], "mix_ms": r["mix_ms"]}), flush=True)
+        return
 
     plan = P.Plan(Xv, opts(True))
 

@@ -176,15 +176,25 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
     __shared__ int64_t cbase[3][TC];
     __shared__ float csign[3][TC];
     __shared__ float lsign[FIRST ? L : 1];
+    // FIRST: every sign vector staged in LDS once (when they fit), so the
+    // per-tile sign products read no global memory
+    constexpr int kSignLds = 2048;
+    __shared__ int8_t sgl[FIRST ? kSignLds : 1];
     const int tid = threadIdx.x;
     const int64_t ncols = J * K;
     const int64_t ntiles = ceil_div(ncols, TC);
     for (int e = tid; e < L; e += NT) tw[e] = twg[e];
-    int moff = 0;
+    int moff = 0, nsg = 0;
     if (FIRST) {
         for (int mm = 0; mm < m; ++mm) moff += (int)xi.dims[mm];
+        for (int mm = 0; mm < xi.order; ++mm) nsg += (int)xi.dims[mm];
         for (int e = tid; e < L; e += NT) lsign[e] = (float)signs[moff + e];
+        if (nsg <= kSignLds)
+            for (int e = tid; e < nsg; e += NT) sgl[e] = signs[e];
     }
+    const int8_t *sgp = (FIRST && nsg <= kSignLds) ? sgl : signs;
+    // 32-bit index arithmetic when the fiber count fits
+    const bool small = ncols < (int64_t)INT32_MAX;
     // fiber offsets (and FIRST: sign products over the other modes) of tile t
     auto tile_info = [&](int64_t t, int slot) {
         for (int c = tid; c < TC; c += NT) {
@@ -194,26 +204,51 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
                 csign[slot][c] = 0.f;
                 continue;
             }
-            int64_t j = q % J, k = q / J;
-            cbase[slot][c] = j + J * L * k;
-            if (FIRST) {
-                float sg = 1.0f;
-                int off = 0;
-                for (int mm = 0; mm < xi.order; ++mm) {
-                    if (mm != m) {
-                        int64_t im;
-                        if (mm < m) {
-                            im = j % xi.dims[mm];
-                            j /= xi.dims[mm];
-                        } else {
-                            im = k % xi.dims[mm];
-                            k /= xi.dims[mm];
+            if (small) {
+                uint32_t j = (uint32_t)q % (uint32_t)J, k = (uint32_t)q / (uint32_t)J;
+                cbase[slot][c] = (int64_t)j + J * L * (int64_t)k;
+                if (FIRST) {
+                    float sg = 1.0f;
+                    int off = 0;
+                    for (int mm = 0; mm < xi.order; ++mm) {
+                        if (mm != m) {
+                            const uint32_t d = (uint32_t)xi.dims[mm];
+                            uint32_t im;
+                            if (mm < m) {
+                                im = j % d;
+                                j /= d;
+                            } else {
+                                im = k % d;
+                                k /= d;
+                            }
+                            sg *= (float)sgp[off + (int)im];
                         }
-                        sg *= (float)signs[off + im];
+                        off += (int)xi.dims[mm];
                     }
-                    off += (int)xi.dims[mm];
+                    csign[slot][c] = sg;
                 }
-                csign[slot][c] = sg;
+            } else {
+                int64_t j = q % J, k = q / J;
+                cbase[slot][c] = j + J * L * k;
+                if (FIRST) {
+                    float sg = 1.0f;
+                    int off = 0;
+                    for (int mm = 0; mm < xi.order; ++mm) {
+                        if (mm != m) {
+                            int64_t im;
+                            if (mm < m) {
+                                im = j % xi.dims[mm];
+                                j /= xi.dims[mm];
+                            } else {
+                                im = k % xi.dims[mm];
+                                k /= xi.dims[mm];
+                            }
+                            sg *= (float)sgp[off + im];
+                        }
+                        off += (int)xi.dims[mm];
+                    }
+                    csign[slot][c] = sg;
+                }
             }
         }
     };
@@ -587,14 +622,20 @@ static hipError_t launch_ct_pass(const FftPlan *fp, const ModeInfo &xi, const vo
     const unsigned nb = (unsigned)ceil_div(J * K, TC);
     const cx<float> *tw = (const cx<float> *)fp->tw;
     const bool xa = (((uintptr_t)X) & 15) == 0, ha = (((uintptr_t)Xhat) & 15) == 0;
-    // persistent grid for the pipelined kernel: as many workgroups as fit per
-    // CU by LDS (at most 8), one pass over the CUs
-    constexpr size_t kLds = (size_t)L * (TC + 1) * 8 + (size_t)L * 8 + TC * 36 + L * 4;
-    const unsigned per_cu = (unsigned)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / kLds));
-    const unsigned np = (unsigned)std::min<int64_t>((int64_t)nb, (int64_t)device_cus() * per_cu);
     // the pipelined kernel holds the next tile in registers: long fibers
     // (more than 8 vectors per thread) would spill, they use mix_pass_ct
     constexpr bool kPipe = (L * TC / 2 + NT - 1) / NT <= 8;
+    // persistent grid for the pipelined kernel: the workgroups that are
+    // resident at once (registers and LDS, as the runtime reports them), one
+    // pass over the CUs; a larger grid would run its tail as a second round
+    auto persistent_grid = [&](auto kernel, unsigned &cache) -> unsigned {
+        if (cache == 0) {
+            int n = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, NT, 0) != hipSuccess || n < 1) n = 1;
+            cache = (unsigned)n;
+        }
+        return (unsigned)std::min<int64_t>((int64_t)nb, (int64_t)device_cus() * cache);
+    };
     if (first) {
         if (xkind != K_F32) return hipErrorInvalidValue;
         if constexpr (L % 4 == 0) {
@@ -606,7 +647,9 @@ static hipError_t launch_ct_pass(const FftPlan *fp, const ModeInfo &xi, const vo
         }
         if constexpr (L % 4 == 0 && kPipe) {
             if (J == 1 && xa && ha) {
-                double *nsp = ex ? ex->normsq_part : nullptr;
+                static unsigned per_cu = 0;
+                const unsigned np = persistent_grid(mix_pass_pipe<L, TC, NT, true>, per_cu);
+                double *nsp = (ex && np <= 4096) ? ex->normsq_part : nullptr;  // partial buffer: 4096 doubles
                 hipLaunchKernelGGL((mix_pass_pipe<L, TC, NT, true>), dim3(np), dim3(NT), 0, st, (const float *)X,
                                    (cx<float> *)Xhat, J, K, xi, m, signs, tw, nsp, (cx<float> *)nullptr);
                 if (nsp) ex->nparts = (int32_t)np;
@@ -620,6 +663,8 @@ static hipError_t launch_ct_pass(const FftPlan *fp, const ModeInfo &xi, const vo
     } else {
         if constexpr (kPipe) {
             if (J > 1 && J % TC == 0 && ha) {
+                static unsigned per_cu = 0;
+                const unsigned np = persistent_grid(mix_pass_pipe<L, TC, NT, false>, per_cu);
                 const bool cp = ex && ex->copy && ex->copy_ld == L && (((uintptr_t)ex->copy) & 15) == 0;
                 hipLaunchKernelGGL((mix_pass_pipe<L, TC, NT, false>), dim3(np), dim3(NT), 0, st,
                                    (const float *)nullptr, (cx<float> *)Xhat, J, K, xi, m, signs, tw,
@@ -651,7 +696,7 @@ static bool launch_fixed_length(int64_t L, const FftPlan *fp, const ModeInfo &xi
         case 150: *err = launch_ct_pass<150, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
         case 200: *err = launch_ct_pass<200, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
         case 300: *err = launch_ct_pass<300, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
-        case 400: *err = launch_ct_pass<400, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
+        case 400: *err = launch_ct_pass<400, 16, 1024>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
         case 1000: *err = launch_ct_pass<1000, 16, 512>(fp, xi, X, xkind, Xhat, m, first, signs, J, K, ex, st); return true;
         default: return false;
     }

@@ -19,6 +19,8 @@
 
 namespace cprand {
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 constexpr int kStepThreads = 512;
 constexpr int kColParts = 16;
 constexpr int kMaxParts = 8;  // partial products summed here (the gathers use at most this many chunks)
@@ -245,42 +247,106 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
         // and rows t / R, t / R + kstride, ..., and sums |A-hat|^2 of its
         // rows; the column norms are then closed in a fixed order.
         const int half = In / 2 + 1;
-        const int kstride = kStepThreads / R;
-        double nsq = 0.0;
-        if (tid < kstride * R) {
-            const int r = tid % R;
-            for (int k = tid / R; k < half; k += kstride) {
-                const int kk = k == 0 ? 0 : In - k;
-                double sr = 0.0, si = 0.0;
-                for (int j = 0; j < R; ++j) {
-                    const double h = B1[j * ld + r];
-                    sr += (Wd[k * R + j] + Wd[kk * R + j]) * h;
-                    si += (Wi[k * R + j] - Wi[kk * R + j]) * h;
+        if (R <= 16) {
+            // FP64 MFMA 16x16x4 over tiles of 16 row pairs: lane (li, lk)
+            // feeds A(row li, k lk) = Y_s(tile row li, 4c + lk) and
+            // B(k lk, col li) = V^{-1}(4c + lk, li), and holds output rows
+            // lk + 4v, column li; per-wave column sums of |A-hat|^2
+            const int wv = tid / kWave, l = tid & (kWave - 1), li = l & 15, lk = l >> 4;
+            constexpr int nw = kStepThreads / kWave;
+            double bo[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int jj = 4 * c + lk;
+                bo[c] = (jj < R && li < R) ? B1[jj * ld + li] : 0.0;
+            }
+            double nsq = 0.0;
+            const int ntile = (half + 15) / 16;
+            for (int tile = wv; tile < ntile; tile += nw) {  // uniform per wave
+                const int k = tile * 16 + li;
+                const bool kin = k < half;
+                const int kk = (k == 0 || !kin) ? 0 : In - k;
+                v4d dre = {0.0, 0.0, 0.0, 0.0}, dim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int jj = 4 * c + lk;
+                    double are = 0.0, aim = 0.0;
+                    if (kin && jj < R) {
+                        are = 0.5 * (Wd[k * R + jj] + Wd[kk * R + jj]);
+                        aim = 0.5 * (Wi[k * R + jj] - Wi[kk * R + jj]);
+                    }
+                    dre = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bo[c], dre, 0, 0, 0);
+                    dim = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, bo[c], dim, 0, 0, 0);
                 }
-                sr *= 0.5;
-                si *= 0.5;
-                Ad[k * R + r] = sr;
-                Ai[k * R + r] = si;
-                const double q2 = sr * sr + si * si;
-                nsq += q2;
-                if (kk != k) {
-                    Ad[kk * R + r] = sr;
-                    Ai[kk * R + r] = -si;
-                    nsq += q2;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int ko = tile * 16 + lk + 4 * v;
+                    if (ko < half && li < R) {
+                        const int kko = ko == 0 ? 0 : In - ko;
+                        const double sr = dre[v], si = dim[v];
+                        Ad[ko * R + li] = sr;
+                        Ai[ko * R + li] = si;
+                        const double q2 = sr * sr + si * si;
+                        nsq += q2;
+                        if (kko != ko) {
+                            Ad[kko * R + li] = sr;
+                            Ai[kko * R + li] = -si;
+                            nsq += q2;
+                        }
+                    }
                 }
             }
+            nsq += __shfl_xor(nsq, 16, kWave);
+            nsq += __shfl_xor(nsq, 32, kWave);
+            if (lk == 0) tmp[wv * 16 + li] = nsq;
+            __syncthreads();
+            if (tid < R) {
+                double s = 0.0;
+                for (int w = 0; w < nw; ++w) s += tmp[w * 16 + tid];
+                const double l = sqrt(s);
+                B2[tid] = l;
+                a.lambda[tid] = l;
+                if (a.snap_lambda) a.snap_lambda[tid] = l;
+            }
+            __syncthreads();
+        } else {
+            const int kstride = kStepThreads / R;
+            double nsq = 0.0;
+            if (tid < kstride * R) {
+                const int r = tid % R;
+                for (int k = tid / R; k < half; k += kstride) {
+                    const int kk = k == 0 ? 0 : In - k;
+                    double sr = 0.0, si = 0.0;
+                    for (int j = 0; j < R; ++j) {
+                        const double h = B1[j * ld + r];
+                        sr += (Wd[k * R + j] + Wd[kk * R + j]) * h;
+                        si += (Wi[k * R + j] - Wi[kk * R + j]) * h;
+                    }
+                    sr *= 0.5;
+                    si *= 0.5;
+                    Ad[k * R + r] = sr;
+                    Ai[k * R + r] = si;
+                    const double q2 = sr * sr + si * si;
+                    nsq += q2;
+                    if (kk != k) {
+                        Ad[kk * R + r] = sr;
+                        Ai[kk * R + r] = -si;
+                        nsq += q2;
+                    }
+                }
+            }
+            tmp[tid] = nsq;
+            __syncthreads();
+            if (tid < R) {
+                double s = 0.0;
+                for (int k0 = 0; k0 < kstride; ++k0) s += tmp[k0 * R + tid];
+                const double l = sqrt(s);
+                B2[tid] = l;
+                a.lambda[tid] = l;
+                if (a.snap_lambda) a.snap_lambda[tid] = l;
+            }
+            __syncthreads();
         }
-        tmp[tid] = nsq;
-        __syncthreads();
-        if (tid < R) {
-            double s = 0.0;
-            for (int k0 = 0; k0 < kstride; ++k0) s += tmp[k0 * R + tid];
-            const double l = sqrt(s);
-            B2[tid] = l;
-            a.lambda[tid] = l;
-            if (a.snap_lambda) a.snap_lambda[tid] = l;
-        }
-        __syncthreads();
         T *Ah = (T *)a.Ahat;
         for (int e = tid; e < In * R; e += kStepThreads) {
             const double l = B2[e % R];
