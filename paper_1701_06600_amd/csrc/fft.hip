@@ -260,8 +260,8 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
             const int e = tid + u * NT;
             r[u] = float4{0.f, 0.f, 0.f, 0.f};
             if (e < NV) {
-                if (FIRST) {  // the tile's fibers are adjacent (J = 1): one contiguous run of L * TC floats
-                    const int c = e / (L / 4), l4 = (e - c * (L / 4)) * 4;
+                if (FIRST) {  // fiber fastest: conflict-free LDS writes, 64 contiguous bytes per fiber per wave
+                    const int c = e % TC, l4 = (e / TC) * 4;
                     if (c < nc) r[u] = *(const float4 *)(X + cbase[slot][c] + l4);
                 } else {
                     const int l = e / (TC / 2), c = (e - l * (TC / 2)) * 2;
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
             if (e >= NV) continue;
             const float4 v = r[u];
             if (FIRST) {
-                const int c = e / (L / 4), l4 = (e - c * (L / 4)) * 4;
+                const int c = e % TC, l4 = (e / TC) * 4;
                 const float sc = c < nc ? csign[cur][c] : 0.f;
                 nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
                 buf[(l4 + 0) * LDT + c] = {v.x * sc * lsign[l4 + 0], 0.f};

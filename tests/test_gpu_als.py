@@ -117,7 +117,10 @@ def test_multi_kernel_step_path_tracks_oracle(mix):
         assert np.allclose(a, b, atol=1e-7)
 
 
-def test_cprand_fixed_proposal_tracks_oracle():
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_cprand_fixed_proposal_tracks_oracle(use_graph):
+    """Fixed importance tables; with direct launches the weighted samples of
+    every step are drawn at setup, with a graph inside the gathers."""
     p = synth.make_problem((30, 40, 50), 4, congruence=0.5, noise=0.01, seed=10, spiky=0.1)
     X = synth.dense_tensor(p)
     qs = [OQ.quantize(OL.leverage_scores(M) / 4, 0.2) for M in p.factors]
@@ -128,6 +131,23 @@ def test_cprand_fixed_proposal_tracks_oracle():
         return OQ.importance_indices(X.shape, n, S, 3, t, qs)
 
     out, A = _run_gpu(X, p.init, 4, S, 3, torch.float64, max_iters=20, proposal=P.PROPOSAL_TABLE,
-                      proposal_cdf=cdfs)
+                      proposal_cdf=cdfs, use_graph=use_graph)
     lam_r, A_r, hist_r = OC.cprand(X, 4, S, p.init, 3, 20, sampler=sampler)
     assert np.max(np.abs(np.array(out["fit_history"]) - np.array(hist_r))) < 1e-8
+
+
+@pytest.mark.parametrize("dims,R", [((21, 16, 9), 5), ((30, 25, 20), 20), ((12, 10, 9, 8), 3)])
+def test_mixed_step_shapes_track_oracle(dims, R):
+    """The fused mixed step on odd and even I_n (rows 0 and I_n/2 pair with
+    themselves), R <= 16 (one-wave inverse, FP64 MFMA solve) and R = 20
+    (blocked inverse, scalar solve), and an order-4 tensor: F-hat history and
+    final factors against the oracle's CPRAND-MIX."""
+    p = synth.make_problem(dims, R, congruence=0.5, noise=0.01, seed=31)
+    X = synth.dense_tensor(p)
+    S, it = max(OC.sample_size(R), 2 * R), 8
+    out, A = _run_gpu(X, p.init, R, S, 41, torch.float64, max_iters=it, mix=P.MIX_FFT)
+    lam_r, A_r, hist_r = OC.cprand_mix(X, R, S, p.init, 41, it)
+    assert np.max(np.abs(np.array(out["fit_history"]) - np.array(hist_r))) < 1e-8
+    assert np.allclose(out["lambda"].cpu().numpy(), lam_r, rtol=1e-7)
+    for a, b in zip(A, A_r):
+        assert np.allclose(a, b, atol=1e-7)
