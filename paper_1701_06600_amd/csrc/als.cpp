@@ -86,6 +86,10 @@ struct cprand_plan {
     void *wtmp = nullptr;   // maxdim x R doubles: summed (or unmixed) MTTKRP of the split path
     double *vsum = nullptr; // R x R: summed Gram of the split path
     void *snapbuf[2] = {};   // factors + lambda after even / odd iterations (run-ahead loop)
+    // samples of every mode step of the run, drawn at setup (direct-launch,
+    // non-adaptive plans, when they fit in kPreSampleBytes)
+    int32_t *pre_idx = nullptr;
+    double *pre_w = nullptr;
     size_t snapbytes = 0;
     int32_t *frow = nullptr; // the fixed fit set: rows [P_hat][N] and tensor values [P_hat][2]
     double *fx = nullptr;
@@ -127,6 +131,8 @@ struct cprand_plan {
 };
 
 namespace {
+
+constexpr size_t kPreSampleBytes = (size_t)64 << 20;
 
 hipError_t dalloc(cprand_plan *p, void **ptr, size_t bytes) {
     if (bytes == 0) bytes = 256;
@@ -297,6 +303,11 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         if (ic) {
             ga.t = ic->t;
             ga.t_dev = nullptr;
+            if (p->pre_idx) {  // drawn at setup
+                const size_t y = (size_t)ic->t * N + n;
+                ga.idx = p->pre_idx + y * p->o.S * N;
+                ga.w = p->pre_w ? p->pre_w + y * p->o.S : nullptr;
+            }
         } else {
             ga.t_dev = p->t_dev;
         }
@@ -612,6 +623,17 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     if (e == hipSuccess) e = dalloc(p, (void **)&p->fx, (size_t)o.P_hat * 16);
     if (e == hipSuccess && p->mix) e = dalloc(p, &p->ysum, (size_t)maxdim * 2 * R * tsz);
     p->adaptive = o.proposal == CPRAND_PROPOSAL_LEARNED || o.proposal == CPRAND_PROPOSAL_MARGINAL;
+    {
+        // the samples depend only on (seed, t, n) unless the proposal adapts:
+        // draw them all at setup for direct-launch loops
+        const size_t steps = (size_t)o.max_iters * N;
+        const size_t bytes = steps * o.S * N * 4 + (o.proposal == CPRAND_PROPOSAL_TABLE ? steps * o.S * 8 : 0);
+        if (e == hipSuccess && !p->adaptive && !o.use_graph && bytes <= kPreSampleBytes && steps <= 65535) {
+            e = dalloc(p, (void **)&p->pre_idx, steps * o.S * N * 4);
+            if (e == hipSuccess && o.proposal == CPRAND_PROPOSAL_TABLE)
+                e = dalloc(p, (void **)&p->pre_w, steps * o.S * 8);
+        }
+    }
     if (e == hipSuccess && p->adaptive) {
         e = dalloc(p, (void **)&p->pstats, (size_t)N * mode_stats_doubles(R) * 8);
         if (e == hipSuccess) e = dalloc(p, (void **)&p->pH, (size_t)R * R * 8);
@@ -758,6 +780,19 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
         if (e == hipSuccess) e = launch_normsq_partial(xi, X->data, p->xkind, p->normpart, &np, st);
         if (e == hipSuccess) e = launch_sqrt_sum(p->normpart, np, p->normX, st);
         if (e == hipSuccess) e = hipEventRecord(tev[1], st);
+    }
+    if (e == hipSuccess && p->pre_idx) {
+        ModeInfo mi{};
+        mi.order = N;
+        for (int m = 0; m < N; ++m) {
+            mi.dims[m] = p->dims[m];
+            mi.strides[m] = 1;
+        }
+        CdfPtrs cdf{};
+        if (p->o.proposal == CPRAND_PROPOSAL_TABLE)
+            for (int m = 0; m < N; ++m) cdf.p[m] = p->o.proposal_cdf[m];
+        e = launch_sample_all(mi, p->o.S, p->o.max_iters, p->o.seed,
+                              p->o.proposal == CPRAND_PROPOSAL_TABLE ? &cdf : nullptr, p->pre_idx, p->pre_w, st);
     }
     // the fixed fit set: rows and tensor values drawn once per run
     if (e == hipSuccess) e = launch_fit_set(fit_args(p, X->data), p->frow, p->fx, st);

@@ -12,6 +12,11 @@ namespace cprand {
 hipError_t launch_sample(const ModeInfo &mi, int32_t S, uint64_t seed, uint64_t t,
                          const uint64_t *t_dev, const CdfPtrs *cdf, int32_t *idx, double *w,
                          hipStream_t st);
+// The samples of every mode step of iterations 0 .. T-1 (uniform or fixed
+// tables): step (t, n) at idx + (t * order + n) * S * order, weights (when w)
+// at w + (t * order + n) * S; the same draws as launch_sample.
+hipError_t launch_sample_all(const ModeInfo &mi, int32_t S, int32_t T, uint64_t seed, const CdfPtrs *cdf,
+                             int32_t *idx, double *w, hipStream_t st);
 
 // ---- sampled MTTKRP -----------------------------------------------------------
 // Element kinds of the gathered tensor.
