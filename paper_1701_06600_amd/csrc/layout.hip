@@ -3,6 +3,8 @@
 // vector), optionally converted (FP32 -> BF16 round-to-nearest-even, or
 // between real types).  A one-time HBM pass; LDS-tiled transpose so both
 // the reads (along mode 0) and the writes (along mode n) are coalesced.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace cprand {
@@ -74,6 +76,39 @@ __global__ __launch_bounds__(256) void transpose_kernel(const Ti *X, To *Y, int6
     }
 }
 
+// The same transpose for 8-byte elements (complex64) when J, L and ld are
+// even and both buffers 16-byte aligned: every access moves two elements
+// (16 bytes), a row of the 64 x 64 tile is 32 lanes.
+__global__ __launch_bounds__(256) void transpose_pair_kernel(const c64 *X, c64 *Y, int64_t J, int64_t L, int64_t ld,
+                                                             int64_t K, int64_t jt) {
+    __shared__ c64 tile[kT][kT + 1];
+    const int64_t bx = blockIdx.x;
+    const int64_t k = bx / jt, j0 = (bx - k * jt) * kT;
+    const int64_t i0 = (int64_t)blockIdx.y * kT;
+    const int c2 = threadIdx.x & 31, r = threadIdx.x >> 5;  // pair column, row within a pass of 8 rows
+    float4 v[kT / 8];
+#pragma unroll
+    for (int p = 0; p < kT / 8; ++p) {
+        const int64_t i = i0 + r + 8 * p, j = j0 + 2 * c2;
+        v[p] = float4{0.f, 0.f, 0.f, 0.f};
+        if (i < L && j < J) v[p] = *(const float4 *)(X + j + J * (i + L * k));
+    }
+#pragma unroll
+    for (int p = 0; p < kT / 8; ++p) {
+        tile[r + 8 * p][2 * c2] = c64{v[p].x, v[p].y};
+        tile[r + 8 * p][2 * c2 + 1] = c64{v[p].z, v[p].w};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kT / 8; ++p) {
+        const int64_t j = j0 + r + 8 * p, i = i0 + 2 * c2;
+        if (j < J && i < ld) {
+            const c64 a = tile[2 * c2][r + 8 * p], b = tile[2 * c2 + 1][r + 8 * p];
+            *(float4 *)(Y + i + ld * (j + J * k)) = float4{a.re, a.im, b.re, b.im};
+        }
+    }
+}
+
 template <typename Ti, typename To>
 static hipError_t launch_lc(const ModeInfo &xi, const void *X, int32_t n, int64_t ld, void *Y,
                             hipStream_t st) {
@@ -89,8 +124,14 @@ static hipError_t launch_lc(const ModeInfo &xi, const void *X, int32_t n, int64_
     } else {
         const int64_t jt = ceil_div(J, kT);
         dim3 grid((unsigned)(jt * K), (unsigned)ceil_div(ld, kT));
-        hipLaunchKernelGGL((transpose_kernel<Ti, To>), grid, dim3(256), 0, st, (const Ti *)X,
-                           (To *)Y, J, L, ld, K, jt);
+        constexpr bool pairable = std::is_same<Ti, c64>::value && std::is_same<To, c64>::value;
+        if (pairable && J % 2 == 0 && L % 2 == 0 && ld % 2 == 0 && ld == L && (((uintptr_t)X) & 15) == 0 &&
+            (((uintptr_t)Y) & 15) == 0)
+            hipLaunchKernelGGL(transpose_pair_kernel, grid, dim3(256), 0, st, (const c64 *)X, (c64 *)Y, J, L, ld, K,
+                               jt);
+        else
+            hipLaunchKernelGGL((transpose_kernel<Ti, To>), grid, dim3(256), 0, st, (const Ti *)X,
+                               (To *)Y, J, L, ld, K, jt);
     }
     return hipGetLastError();
 }

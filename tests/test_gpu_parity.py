@@ -290,3 +290,19 @@ def test_layout_copy_exact_and_bf16_rne():
         for i in list(np.ndindex(*dims))[::7]:
             off = sum(ii * s for ii, s in zip(i, Yb.strides))
             assert gotb[off] == want[i]
+
+
+@pytest.mark.parametrize("dims", [(66, 70, 3), (21, 16, 9)])
+def test_layout_copy_complex_exact(dims):
+    """Mode-major copies of a complex64 tensor (the mixed tensor's copies):
+    bit-exact for every mode, with even sizes (16-byte pair transpose, edge
+    tiles) and odd ones (element transpose)."""
+    rng = _rng(17)
+    X = (rng.standard_normal(dims) + 1j * rng.standard_normal(dims)).astype(np.complex64)
+    Xv = view_of(X, torch.complex64)
+    idx = np.indices(dims).reshape(len(dims), -1)
+    for n in range(len(dims)):
+        Y = P.mode_major_copy(Xv, n)
+        flat = Y.data.cpu().numpy()
+        off = sum(idx[m] * Y.strides[m] for m in range(len(dims)))
+        assert np.array_equal(flat[off], X.reshape(-1)[np.ravel_multi_index(idx, dims)]), n
