@@ -24,6 +24,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kStepThreads = 512;
 constexpr int kColParts = 16;
 constexpr int kMaxParts = 8;  // partial products summed here (the gathers use at most this many chunks)
+constexpr int kMixGroups = 3; // mixed products: (column, VL rows) groups per thread per pass, loads in flight together
 static_assert(kColParts * kMaxRank >= kStepThreads, "tmp holds one double per thread");
 
 template <typename T>
@@ -110,10 +111,10 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
             const T *y = (const T *)a.W;
             const size_t cstride = (size_t)2 * R * In;
             const int ng = R * (In / VL);
-            for (int g0 = yt; g0 < ng; g0 += 2 * ys) {
-                V16 vr[2][kMaxParts], vi[2][kMaxParts];
+            for (int g0 = yt; g0 < ng; g0 += kMixGroups * ys) {
+                V16 vr[kMixGroups][kMaxParts], vi[kMixGroups][kMaxParts];
     #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < kMixGroups; ++h) {
                     const int g = g0 + h * ys;
                     const int c = g / (In / VL), l0 = (g - c * (In / VL)) * VL;
     #pragma unroll
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
                     }
                 }
     #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < kMixGroups; ++h) {
                     const int g = g0 + h * ys;
                     if (g >= ng) continue;
                     const int c = g / (In / VL), l0 = (g - c * (In / VL)) * VL;
