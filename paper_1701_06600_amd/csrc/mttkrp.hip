@@ -40,17 +40,6 @@ __device__ inline v4d mfma16(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Exact select by bit masks (a ternary on a loaded value can be compiled as
-// a branch around the load, which then has to be waited on at the join).
-__device__ inline float bitsel(bool c, float a, float b) {
-    const int m = -(int)c;
-    return __int_as_float((__float_as_int(a) & m) | (__float_as_int(b) & ~m));
-}
-__device__ inline double bitsel(bool c, double a, double b) {
-    const long long m = -(long long)c;
-    return __longlong_as_double((__double_as_longlong(a) & m) | (__double_as_longlong(b) & ~m));
-}
-
 template <typename T, bool CPLX>
 struct Geo {
     static constexpr int NV = 16 / (int)sizeof(T);          // reals per 16-byte vector
@@ -201,52 +190,56 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
     const int rb0 = blockIdx.x * a.rows_wg + wv * G::RPW;
     if (rb0 < row_end) load_fibers<T, CPLX, CONTIG>(v, xp, s_base, ns, 0, rb0 + G::VE * li, lk, In, sn);
 
-    // ---- (2) sampled Khatri-Rao rows, four elements per thread per pass:
-    // every factor load of the four is issued before the products (a load
-    // whose mode does not take part reads row 0 of a factor that does, and
-    // its value is replaced by 1 with a bit select, so no load sits in a
-    // branch); the product runs over the modes in order, as before
+    // ---- (2) sampled Khatri-Rao rows, up to four elements per thread per
+    // pass with all their factor loads issued before the products.  Loads
+    // run over the N-1 modes that take part (a uniform bound); elements past
+    // the end read element 0 and are not stored.  The product runs over the
+    // modes in order, as before.
     {
-        const int m0 = (n == 0) ? 1 : 0;  // a mode that takes part
+        const int nm = N - 1;
+        const int tot = ns * R;
         constexpr int KE = 4;
-        for (int e0 = tid; e0 < ns * R; e0 += KE * nthr) {
-            T vr[KE][kMaxOrder], vi[KE][kMaxOrder];
+        const int ke = min(KE, (tot + nthr - 1) / nthr);  // passes fit the elements
+        for (int e0 = tid; e0 < tot; e0 += ke * nthr) {
+            T vr[KE][kMaxOrder - 1], vi[KE][kMaxOrder - 1];
 #pragma unroll
             for (int h = 0; h < KE; ++h) {
-                const int e = e0 + h * nthr;
-                const bool ok = e < ns * R;
-                const int sl = ok ? e / R : 0, r = ok ? e - (e / R) * R : 0;
+                if (h >= ke) break;  // uniform
+                const int e = min(e0 + h * nthr, tot - 1);
+                const int sl = e / R, r = e - (e / R) * R;
 #pragma unroll
-                for (int m = 0; m < kMaxOrder; ++m) {
-                    const bool use = ok && m < N && m != n;
-                    const T *Am = (const T *)a.A.p[use ? m : m0];
-                    const int64_t o = use ? (int64_t)s_idx[sl * N + m] * R + r : 0;
+                for (int j = 0; j < kMaxOrder - 1; ++j) {
+                    if (j >= nm) break;  // uniform
+                    const int m = j < n ? j : j + 1;
+                    const T *Am = (const T *)a.A.p[m];
+                    const int64_t o = (int64_t)s_idx[sl * N + m] * R + r;
                     if (CPLX) {
-                        vr[h][m] = bitsel(use, Am[2 * o], (T)1);
-                        vi[h][m] = bitsel(use, Am[2 * o + 1], (T)0);
+                        vr[h][j] = Am[2 * o];
+                        vi[h][j] = Am[2 * o + 1];
                     } else {
-                        vr[h][m] = bitsel(use, Am[o], (T)1);
+                        vr[h][j] = Am[o];
                     }
                 }
             }
 #pragma unroll
             for (int h = 0; h < KE; ++h) {
+                if (h >= ke) break;
                 const int e = e0 + h * nthr;
-                if (e >= ns * R) continue;
+                if (e >= tot) continue;
                 const int sl = e / R, r = e - sl * R;
                 if (!CPLX) {
                     T z = (T)1;
 #pragma unroll
-                    for (int m = 0; m < kMaxOrder; ++m)
-                        if (m < N && m != n) z *= vr[h][m];
+                    for (int j = 0; j < kMaxOrder - 1; ++j)
+                        if (j < nm) z *= vr[h][j];
                     Zr[sl * LDB + r] = z;
                     if (WEIGHTED) Bre[sl * LDB + r] = (T)(s_w[sl] * (double)z);
                 } else {
                     T zr = (T)1, zi = (T)0;
 #pragma unroll
-                    for (int m = 0; m < kMaxOrder; ++m) {
-                        if (!(m < N && m != n)) continue;
-                        const T ar = vr[h][m], ai = vi[h][m];
+                    for (int j = 0; j < kMaxOrder - 1; ++j) {
+                        if (j >= nm) break;
+                        const T ar = vr[h][j], ai = vi[h][j];
                         const T nr = zr * ar - zi * ai;
                         const T ni = zr * ai + zi * ar;
                         zr = nr;
@@ -263,21 +256,56 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
     }
     __syncthreads();
 
-    // ---- (3) Gram of the chunk on FP64 MFMA 16x16x4: V(r, q) = sum_k
-    // w_k z_k(r) z_k(q) (complex: zr zr^T + zi zi^T) over the chunk's
-    // samples k.  Output tiles (rt, qt), qt >= rt, are dealt to the (row
-    // block, wave) pairs of the chunk; lane (li, lk) feeds A(r = 16 rt + li,
-    // k = 4 kk + lk) and B(k, q = 16 qt + li) and holds rows 16 rt + lk + 4 v
-    // of column 16 qt + li.  Columns at or past R are masked (for complex
-    // data they hold the imaginary block).
-    {
-        const int nrb = (int)gridDim.x, rb = (int)blockIdx.x;
+    // ---- (3) Gram of the chunk, V(r, q) = sum_k w_k z_k(r) z_k(q) (complex:
+    // zr zr^T + zi zi^T) over the chunk's samples k, FP64, fixed order.
+    // No barrier: waves without Gram work go on to the fiber products.
+    double *vp = a.vpart + (size_t)chunk * R * R;
+    const int nrb = (int)gridDim.x, rb = (int)blockIdx.x;
+    if (R <= 16) {
+        // one output tile: entries p = (r, q) dealt to the chunk's row blocks
+        // (p mod row blocks); tpp lanes share an entry, each summing every
+        // tpp-th sample, and a shuffle tree over the tpp lanes closes the sum
+        const int nmine = (R * R - rb + nrb - 1) / nrb;  // entries of this block
+        int tpp = 1;
+        while (tpp < 16 && 2 * tpp * nmine <= nthr) tpp *= 2;
+        const int per = nthr / tpp;  // entries per pass
+        for (int base = 0; base < nmine; base += per) {
+            const int k = base + tid / tpp, part = tid & (tpp - 1);
+            const int p = rb + nrb * k;
+            const int r = p / R, q = p - (p / R) * R;
+            const bool act = k < nmine && q >= r;
+            double acc = 0.0;
+            if (act) {
+                for (int sl = part; sl < ns; sl += tpp) {
+                    if (!CPLX) {
+                        double t = (double)Zr[sl * LDB + r] * (double)Zr[sl * LDB + q];
+                        if (WEIGHTED) t *= s_w[sl];
+                        acc += t;
+                    } else {
+                        acc += (double)Bre[sl * LDB + r] * (double)Bre[sl * LDB + q] +
+                               (double)Bim[sl * LDB + r] * (double)Bim[sl * LDB + q];
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1)
+                if (o < tpp) acc += __shfl_xor(acc, o, 64);  // uniform: tpp is the same in every lane
+            if (act && part == 0) {
+                vp[r * R + q] = acc;
+                vp[q * R + r] = acc;
+            }
+        }
+    } else {
+        // FP64 MFMA 16x16x4: output tiles (rt, qt), qt >= rt, dealt to the
+        // chunk's (row block, wave) pairs.  Lane (li, lk) feeds A(r = 16 rt +
+        // li, k = 4 kk + lk) and B(k, q = 16 qt + li) and holds rows 16 rt + lk
+        // + 4 v of column 16 qt + li.  Columns at or past R are masked (for
+        // complex data they hold the imaginary block).
         const int wv3 = tid >> 6, l3 = tid & 63, li3 = l3 & 15, lk3 = l3 >> 4;
         const int nwv = nthr >> 6;
         const int nt16 = (R + 15) / 16;
         const int ntiles = nt16 * (nt16 + 1) / 2;
         const int ksteps = (ns + 3) / 4;  // rows past ns are zero (and have zero weight)
-        double *vp = a.vpart + (size_t)chunk * R * R;
         for (int tix = rb + nrb * wv3; tix < ntiles; tix += nrb * nwv) {  // uniform per wave
             int rt = 0, rem = tix;
             while (rem >= nt16 - rt) {
