@@ -156,10 +156,13 @@ __device__ __forceinline__ int gj_wave_regs(double (&v)[4], int R, double maxdia
         if (!(piv > 1e-12 * maxdiag)) return 1;  // uniform across the wave
         const double inv = 1.0 / piv;
         const double rowp = __shfl(vk, ((k & 3) << 4) | j, kWave) * inv;  // M(k, j) / M(k, k)
+        double c[4];  // pivot-column fetches, all issued before any is used
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = __shfl(v[q], (l & 48) | k, kWave);  // M(i0 + 4 q, k)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = i0 + 4 * q;
-            const double ci = __shfl(v[q], (l & 48) | k, kWave);  // M(i, k)
+            const double ci = c[q];
             const double other = fma(-ci, rowp, v[q]);
             const double on_col = -ci * inv;
             const double on_row = bsel(j == k, inv, rowp);
@@ -181,6 +184,55 @@ __device__ __forceinline__ int gj_wave(double *B1, int R, int ld, double maxdiag
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int i = i0 + 4 * q;
+        if (i < R && j < R) B1[i * ld + j] = v[q];
+    }
+    return 0;
+}
+
+// Gauss-Jordan inverse of an R x R matrix, 16 < R <= 32, by one wave in
+// registers: lane l holds column l % 32 of rows l / 32 + 2 q (q < 16), zero
+// outside R x R (padding rows and columns stay zero).  Same pivot test and
+// update as gj_wave_regs.
+__device__ __forceinline__ int gj_wave32_regs(double (&v)[16], int R, double maxdiag) {
+    const int l = threadIdx.x & (kWave - 1), j = l & 31, i0 = l >> 5;
+    for (int k = 0; k < R; ++k) {
+        const int kq = k >> 1;  // slot of row k (uniform)
+        double vk = v[0];
+#pragma unroll
+        for (int q = 1; q < 16; ++q) vk = (kq == q) ? v[q] : vk;
+        const double piv = __shfl(vk, ((k & 1) << 5) | k, kWave);
+        if (!(piv > 1e-12 * maxdiag)) return 1;  // uniform across the wave
+        const double inv = 1.0 / piv;
+        const double rowp = __shfl(vk, ((k & 1) << 5) | j, kWave) * inv;  // M(k, j) / M(k, k)
+        // all sixteen pivot-column fetches are issued before any is used
+        double c[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) c[q] = __shfl(v[q], (l & 32) | k, kWave);  // M(i0 + 2 q, k)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = i0 + 2 * q;
+            const double ci = c[q];
+            const double other = fma(-ci, rowp, v[q]);
+            const double on_col = -ci * inv;
+            const double on_row = bsel(j == k, inv, rowp);
+            v[q] = bsel(i == k, on_row, bsel(j == k, on_col, other));
+        }
+    }
+    return 0;
+}
+
+__device__ __forceinline__ int gj_wave32(double *B1, int R, int ld, double maxdiag) {
+    const int l = threadIdx.x, j = l & 31, i0 = l >> 5;
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = i0 + 2 * q;
+        v[q] = (i < R && j < R) ? B1[i * ld + j] : 0.0;
+    }
+    if (gj_wave32_regs(v, R, maxdiag)) return 1;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = i0 + 2 * q;
         if (i < R && j < R) B1[i * ld + j] = v[q];
     }
     return 0;
@@ -345,10 +397,10 @@ __device__ __forceinline__ int spd_inverse(double *B1, double *B2, const double 
     int bad = 0;
     const double maxdiag = diag_absmax(B1, R, ld, &bad);
     int failed = (bad || !(maxdiag > 0.0)) ? 1 : 0;
-    if (!failed && R <= 16) {
+    if (!failed && R <= 32) {
         __shared__ int s_failed;
         if (tid < kWave) {
-            const int f = gj_wave(B1, R, ld, maxdiag);
+            const int f = R <= 16 ? gj_wave(B1, R, ld, maxdiag) : gj_wave32(B1, R, ld, maxdiag);
             if (tid == 0) s_failed = f;
         }
         __syncthreads();
