@@ -429,7 +429,7 @@ def combined_leg(P, synth, torch, dev, theta):
                              ("learned_fp32", P.PROPOSAL_LEARNED, P.PREC_NATIVE),
                              ("uniform_fp32", P.PROPOSAL_UNIFORM, P.PREC_NATIVE)):
         best = None
-        for k in (5, 10, 15, 20, 30, 40, 60, 80, 120, 160, 200):
+        for k in (5, 10, 15, 20, 25, 30, 35, 40, 45, 50, 60, 70, 80, 100, 120, 160, 200):
             r = run(prop, P.MIX_NONE, prec, k, False)
             best = r
             if r["exact_fit"] >= target:

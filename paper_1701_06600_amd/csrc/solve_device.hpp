@@ -189,51 +189,66 @@ __device__ __forceinline__ int gj_wave(double *B1, int R, int ld, double maxdiag
     return 0;
 }
 
-// Gauss-Jordan inverse of an R x R matrix, 16 < R <= 32, by one wave in
-// registers: lane l holds column l % 32 of rows l / 32 + 2 q (q < 16), zero
-// outside R x R (padding rows and columns stay zero).  Same pivot test and
-// update as gj_wave_regs.
-__device__ __forceinline__ int gj_wave32_regs(double (&v)[16], int R, double maxdiag) {
-    const int l = threadIdx.x & (kWave - 1), j = l & 31, i0 = l >> 5;
-    for (int k = 0; k < R; ++k) {
-        const int kq = k >> 1;  // slot of row k (uniform)
-        double vk = v[0];
+// Gauss-Jordan inverse of B1, 16 < R <= C (C = 32 or 64), by the first four
+// waves in registers, zero-padded to C x C (padding rows and columns stay
+// zero).  Wave w holds rows w C/4 .. (w+1) C/4 - 1: lane l holds column
+// l % C of rows w C/4 + l / C + (64 / C) q.  Step k: the lanes holding row k
+// write it to rowbuf[(k & 1) C ..] (2 C doubles of LDS), one barrier, then
+// every thread reads M(k, k) and M(k, j) from there and takes M(i, k) of its
+// own rows from the lane of its own wave that holds column k, so a step costs
+// one barrier and no division on the owner's side.  The row loop is unrolled
+// over the slots of a lane so that row k's slot is a constant.  Returns 1 on
+// a pivot below 1e-12 maxdiag (the same value in every thread, so the whole
+// block leaves together; B1 is then untouched).  Every thread of the block
+// calls it (blockDim.x >= 256; further waves only meet the barriers).
+template <int C>
+__device__ __forceinline__ int gj_rows(double *B1, double *rowbuf, int R, int ld, double maxdiag) {
+    constexpr int H = kWave / C;  // row groups in a wave
+    constexpr int RW = C / 4;     // rows per wave
+    constexpr int NQ = RW / H;    // rows per lane
+    const int tid = threadIdx.x, w = tid / kWave, l = tid & (kWave - 1);
+    const int j = l % C, h = l / C, src = h * C;
+    const bool act = w < 4;
+    const double thr = 1e-12 * maxdiag;
+    double v[NQ];
 #pragma unroll
-        for (int q = 1; q < 16; ++q) vk = (kq == q) ? v[q] : vk;
-        const double piv = __shfl(vk, ((k & 1) << 5) | k, kWave);
-        if (!(piv > 1e-12 * maxdiag)) return 1;  // uniform across the wave
-        const double inv = 1.0 / piv;
-        const double rowp = __shfl(vk, ((k & 1) << 5) | j, kWave) * inv;  // M(k, j) / M(k, k)
-        // all sixteen pivot-column fetches are issued before any is used
-        double c[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) c[q] = __shfl(v[q], (l & 32) | k, kWave);  // M(i0 + 2 q, k)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = i0 + 2 * q;
-            const double ci = c[q];
-            const double other = fma(-ci, rowp, v[q]);
-            const double on_col = -ci * inv;
-            const double on_row = bsel(j == k, inv, rowp);
-            v[q] = bsel(i == k, on_row, bsel(j == k, on_col, other));
-        }
+    for (int q = 0; q < NQ; ++q) {
+        const int i = w * RW + h + H * q;
+        v[q] = (act && i < R && j < R) ? B1[i * ld + j] : 0.0;
     }
-    return 0;
-}
-
-__device__ __forceinline__ int gj_wave32(double *B1, int R, int ld, double maxdiag) {
-    const int l = threadIdx.x, j = l & 31, i0 = l >> 5;
-    double v[16];
+    for (int kw = 0; kw < 4; ++kw) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int i = i0 + 2 * q;
-        v[q] = (i < R && j < R) ? B1[i * ld + j] : 0.0;
+        for (int kq = 0; kq < NQ; ++kq)
+#pragma unroll
+            for (int kh = 0; kh < H; ++kh) {
+                const int k = kw * RW + kh + H * kq;
+                if (k >= R) goto done;  // uniform
+                double *buf = rowbuf + (k & 1) * C;
+                if (w == kw && h == kh) buf[j] = v[kq];
+                double c[NQ];  // M(i, k) of this lane's rows, all issued before the barrier
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) c[q] = __shfl(v[q], src + k, kWave);
+                __syncthreads();
+                const double piv = buf[k];
+                const double rk = buf[j];
+                if (!(piv > thr)) return 1;
+                const double inv = 1.0 / piv;
+                const double rowp = rk * inv;  // M(k, j) / M(k, k)
+                const double on_row = bsel(j == k, inv, rowp);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const double other = fma(-c[q], rowp, v[q]);
+                    const double on_col = -c[q] * inv;
+                    const bool rowk = (q == kq) && (w == kw) && (h == kh);
+                    v[q] = bsel(rowk, on_row, bsel(j == k, on_col, other));
+                }
+            }
     }
-    if (gj_wave32_regs(v, R, maxdiag)) return 1;
+done:
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int i = i0 + 2 * q;
-        if (i < R && j < R) B1[i * ld + j] = v[q];
+    for (int q = 0; q < NQ; ++q) {
+        const int i = w * RW + h + H * q;
+        if (act && i < R && j < R) B1[i * ld + j] = v[q];
     }
     return 0;
 }
@@ -262,101 +277,6 @@ __device__ __forceinline__ int gj_wave_from_regs(double (&v)[4], double *B1, dou
     for (int q = 0; q < 4; ++q) {
         const int i = i0 + 4 * q;
         if (i < R && j < R) B1[i * ld + j] = v[q];
-    }
-    return 0;
-}
-
-// Blocked Gauss-Jordan elimination of the R x R matrix M (stride ld) with
-// 4 x 4 pivot blocks: the matrix is padded to Rp = 4 ceil(R / 4) with the
-// identity (padding is read, never stored, and stays the identity), thread
-// t < (Rp / 4)^2 owns the 4 x 4 tile (t / (Rp/4), t % (Rp/4)) in registers,
-// and block step kb (K = 4 kb .. 4 kb + 3) does, with P = M(K, K):
-//   M(K, K) <- P^{-1},  M(K, j) <- P^{-1} M(K, j),  M(i, K) <- -M(i, K) P^{-1},
-//   M(i, j) <- M(i, j) - M(i, K) P^{-1} M(K, j)      (i, j not in K),
-// which is four scalar Gauss-Jordan steps at once.  P^{-1} comes from four
-// scalar steps on P in every thread's registers; their pivots are the
-// pivots of scalar elimination, tested against 1e-12 maxdiag.  Returns 1
-// on a failed pivot (M is then partly eliminated; the caller restores it).
-__device__ inline double mpad(const double *M, int R, int ld, int i, int j) {
-    const double x = M[min(i, R - 1) * ld + min(j, R - 1)];  // always a valid address
-    return (i < R && j < R) ? x : (i == j ? 1.0 : 0.0);
-}
-
-__device__ __forceinline__ int gj_block4(double *M, int R, int ld, double maxdiag) {
-    const int tid = threadIdx.x;
-    const int nbk = (R + 3) >> 2;
-    const bool own = tid < nbk * nbk;
-    const int ti = own ? tid / nbk : 0, tj = own ? tid - (tid / nbk) * nbk : 0;
-    double v[4][4];
-    int addr[4][4];  // where each tile entry is stored: padding entries go to the unused column R
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int i = 4 * ti + a, j = 4 * tj + b;
-            v[a][b] = mpad(M, R, ld, i, j);
-            addr[a][b] = (own && i < R && j < R) ? i * ld + j : min(i, R - 1) * ld + R;
-        }
-    const double thr = 1e-12 * maxdiag;
-    for (int kb = 0; kb < nbk; ++kb) {
-        double P[4][4], Rw[4][4], Cc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                P[a][b] = mpad(M, R, ld, 4 * kb + a, 4 * kb + b);
-                Rw[a][b] = mpad(M, R, ld, 4 * kb + a, 4 * tj + b);  // M(K, cols of the tile)
-                Cc[a][b] = mpad(M, R, ld, 4 * ti + a, 4 * kb + b);  // M(rows of the tile, K)
-            }
-        __syncthreads();  // every read of this step precedes every write
-        // P^{-1} by four in-place scalar steps (identical in every thread)
-        bool bad = false;
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            bad = bad || !(P[p][p] > thr);
-            const double inv = 1.0 / P[p][p];
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (b != p) P[p][b] *= inv;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                if (a == p) continue;
-                const double f = P[a][p];
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (b != p) P[a][b] = fma(-f, P[p][b], P[a][b]);
-                P[a][p] = -f * inv;
-            }
-            P[p][p] = inv;
-        }
-        if (bad) return 1;  // uniform: every thread has the same P
-        double Rn[4][4];  // P^{-1} M(K, tile cols): the new pivot rows
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                double t = 0.0;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) t = fma(P[a][c], Rw[c][b], t);
-                Rn[a][b] = t;
-            }
-        const bool krow = ti == kb, kcol = tj == kb;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                double cpi = 0.0, upd = v[a][b];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    cpi = fma(-Cc[a][c], P[c][b], cpi);  // -(M(i, K) P^{-1})(a, b)
-                    upd = fma(-Cc[a][c], Rn[c][b], upd);
-                }
-                const double r = kcol ? P[a][b] : Rn[a][b];
-                const double o = kcol ? cpi : upd;
-                v[a][b] = krow ? r : o;
-                M[addr[a][b]] = v[a][b];
-            }
-        __syncthreads();
     }
     return 0;
 }
@@ -397,16 +317,17 @@ __device__ __forceinline__ int spd_inverse(double *B1, double *B2, const double 
     int bad = 0;
     const double maxdiag = diag_absmax(B1, R, ld, &bad);
     int failed = (bad || !(maxdiag > 0.0)) ? 1 : 0;
-    if (!failed && R <= 32) {
+    if (!failed && R <= 16) {
         __shared__ int s_failed;
         if (tid < kWave) {
-            const int f = R <= 16 ? gj_wave(B1, R, ld, maxdiag) : gj_wave32(B1, R, ld, maxdiag);
+            const int f = gj_wave(B1, R, ld, maxdiag);
             if (tid == 0) s_failed = f;
         }
         __syncthreads();
         failed = s_failed;
     } else if (!failed) {
-        failed = gj_block4(B1, R, ld, maxdiag);
+        failed = R <= 32 ? gj_rows<32>(B1, B2, R, ld, maxdiag) : gj_rows<64>(B1, B2, R, ld, maxdiag);
+        __syncthreads();
     }
     if (!failed) return 0;
     spd_pinv(B1, B2, B3, tmp, R, ld, cs, pairs);

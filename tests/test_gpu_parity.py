@@ -161,7 +161,7 @@ def test_mttkrp_bf16_error_bound():
 
 # --------------------------------------------------------------------------
 # solve and normalise
-@pytest.mark.parametrize("In,R", [(50, 5), (401, 10), (1000, 50), (33, 64)])
+@pytest.mark.parametrize("In,R", [(50, 5), (401, 10), (70, 17), (40, 25), (64, 32), (90, 33), (1000, 50), (33, 64)])
 def test_solve_matches_numpy(In, R):
     rng = _rng(In + R)
     Z = rng.standard_normal((3 * R, R))
@@ -175,12 +175,12 @@ def test_solve_matches_numpy(In, R):
     assert int(info.item()) == 0
 
 
-def test_solve_singular_uses_pseudoinverse():
-    rng = _rng(3)
-    R = 6
-    Z = rng.standard_normal((4, R))          # rank 4 < R
+@pytest.mark.parametrize("R,rk", [(6, 4), (24, 12), (40, 30)])
+def test_solve_singular_uses_pseudoinverse(R, rk):
+    rng = _rng(3 + R)
+    Z = rng.standard_normal((rk, R))         # rank rk < R
     V = Z.T @ Z
-    W = rng.standard_normal((20, 4)) @ Z      # right-hand side in the row space
+    W = rng.standard_normal((20, rk)) @ Z     # right-hand side in the row space
     A, lam, info = P.cprand_solve(dev(V), dev(W))
     assert int(info.item()) == P.W_PINV
     ref = W @ np.linalg.pinv(V, rcond=1e-10)
