@@ -161,20 +161,26 @@ __global__ __launch_bounds__(NT) void mix_pass_ct(const Tin *X, cx<float> *Xh, i
 // persistent grid (a few workgroups per CU) walks the tiles t = blockIdx.x,
 // blockIdx.x + gridDim.x, ...; the global loads of the next tile are issued
 // into registers before the FFT of the current tile, so HBM traffic overlaps
-// the LDS work.  Same arithmetic and output as mix_pass_ct.
+// the LDS work.  The first pass (real input) transforms two real fibers
+// with one complex FFT, x in the real and y in the imaginary part of
+// z = x + i y, and splits the result by conjugate symmetry:
+//   X(k) = (Z(k) + conj Z(L-k)) / 2,  Y(k) = (Z(k) - conj Z(L-k)) / (2 i),
+// so a tile holds 2 TC fibers and the FFT work per element halves.  Other
+// passes: same arithmetic and output as mix_pass_ct.
 template <int L, int TC, int NT, bool FIRST>
 __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *Xh, int64_t J, int64_t K, ModeInfo xi,
                                                     int m, const int8_t *signs, const cx<float> *twg,
                                                     double *normsq_part, cx<float> *copy) {
     constexpr int LDT = TC + 1;
-    constexpr int NV = FIRST ? L * TC / 4 : L * TC / 2;  // float4 per tile
+    constexpr int FC = FIRST ? 2 * TC : TC;              // fibers per tile
+    constexpr int NV = FIRST ? L * FC / 4 : L * TC / 2;  // float4 per tile
     constexpr int PF = (NV + NT - 1) / NT;                // float4 per thread
     __shared__ cx<float> buf[L * LDT];
     __shared__ cx<float> tw[L];
     // tile offsets and signs in three slots: the slot written for the next
     // tile was last read two iterations ago, before the previous barrier
-    __shared__ int64_t cbase[3][TC];
-    __shared__ float csign[3][TC];
+    __shared__ int64_t cbase[3][FC];
+    __shared__ float csign[3][FC];
     __shared__ float lsign[FIRST ? L : 1];
     // FIRST: every sign vector staged in LDS once (when they fit), so the
     // per-tile sign products read no global memory
@@ -182,7 +188,7 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
     __shared__ int8_t sgl[FIRST ? kSignLds : 1];
     const int tid = threadIdx.x;
     const int64_t ncols = J * K;
-    const int64_t ntiles = ceil_div(ncols, TC);
+    const int64_t ntiles = ceil_div(ncols, FC);
     for (int e = tid; e < L; e += NT) tw[e] = twg[e];
     int moff = 0, nsg = 0;
     if (FIRST) {
@@ -197,8 +203,8 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
     const bool small = ncols < (int64_t)INT32_MAX;
     // fiber offsets (and FIRST: sign products over the other modes) of tile t
     auto tile_info = [&](int64_t t, int slot) {
-        for (int c = tid; c < TC; c += NT) {
-            const int64_t q = t * TC + c;
+        for (int c = tid; c < FC; c += NT) {
+            const int64_t q = t * FC + c;
             if (q >= ncols) {
                 cbase[slot][c] = 0;
                 csign[slot][c] = 0.f;
@@ -252,7 +258,7 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
             }
         }
     };
-    auto tile_nc = [&](int64_t t) { return (int)min((int64_t)TC, ncols - t * TC); };
+    auto tile_nc = [&](int64_t t) { return (int)min((int64_t)FC, ncols - t * FC); };
     float4 r[PF];
     auto issue_loads = [&](int slot, int nc) {
 #pragma unroll
@@ -260,8 +266,8 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
             const int e = tid + u * NT;
             r[u] = float4{0.f, 0.f, 0.f, 0.f};
             if (e < NV) {
-                if (FIRST) {  // fiber fastest: conflict-free LDS writes, 64 contiguous bytes per fiber per wave
-                    const int c = e % TC, l4 = (e / TC) * 4;
+                if (FIRST) {  // fiber fastest: conflict-free LDS writes
+                    const int c = e % FC, l4 = (e / FC) * 4;
                     if (c < nc) r[u] = *(const float4 *)(X + cbase[slot][c] + l4);
                 } else {
                     const int l = e / (TC / 2), c = (e - l * (TC / 2)) * 2;
@@ -293,13 +299,16 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
             if (e >= NV) continue;
             const float4 v = r[u];
             if (FIRST) {
-                const int c = e % TC, l4 = (e / TC) * 4;
+                // fiber c goes to the real (even c) or imaginary (odd c) part of column c / 2;
+                // fibers past the end write zeros
+                const int c = e % FC, l4 = (e / FC) * 4;
                 const float sc = c < nc ? csign[cur][c] : 0.f;
                 nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
-                buf[(l4 + 0) * LDT + c] = {v.x * sc * lsign[l4 + 0], 0.f};
-                buf[(l4 + 1) * LDT + c] = {v.y * sc * lsign[l4 + 1], 0.f};
-                buf[(l4 + 2) * LDT + c] = {v.z * sc * lsign[l4 + 2], 0.f};
-                buf[(l4 + 3) * LDT + c] = {v.w * sc * lsign[l4 + 3], 0.f};
+                float *bf = (float *)buf + 2 * (l4 * LDT + (c >> 1)) + (c & 1);
+                bf[0] = v.x * sc * lsign[l4 + 0];
+                bf[2 * LDT] = v.y * sc * lsign[l4 + 1];
+                bf[4 * LDT] = v.z * sc * lsign[l4 + 2];
+                bf[6 * LDT] = v.w * sc * lsign[l4 + 3];
             } else {
                 const int l = e / (TC / 2), c = (e - l * (TC / 2)) * 2;
                 buf[l * LDT + c] = {v.x, v.y};
@@ -312,11 +321,19 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
         fft_ct<float, L, TC, NT, -1>(buf, tw);
         __syncthreads();
         if (FIRST) {
-            for (int e = tid; e < L * TC / 2; e += NT) {
+            const float hs = 0.5f * scale;
+            for (int e = tid; e < L * FC / 2; e += NT) {
                 const int c = e / (L / 2), l2 = (e - c * (L / 2)) * 2;
                 if (c < nc) {
-                    const cx<float> a = buf[l2 * LDT + c], b = buf[(l2 + 1) * LDT + c];
-                    *(float4 *)(Xh + cbase[cur][c] + l2) = {a.re * scale, a.im * scale, b.re * scale, b.im * scale};
+                    const int cc = c >> 1, m0 = l2 == 0 ? 0 : L - l2, m1 = L - l2 - 1;
+                    const cx<float> z0 = buf[l2 * LDT + cc], z1 = buf[(l2 + 1) * LDT + cc];
+                    const cx<float> w0 = buf[m0 * LDT + cc], w1 = buf[m1 * LDT + cc];
+                    float4 o;
+                    if (c & 1)  // (Z(k) - conj Z(L-k)) / (2 i)
+                        o = {(z0.im + w0.im) * hs, (w0.re - z0.re) * hs, (z1.im + w1.im) * hs, (w1.re - z1.re) * hs};
+                    else        // (Z(k) + conj Z(L-k)) / 2
+                        o = {(z0.re + w0.re) * hs, (z0.im - w0.im) * hs, (z1.re + w1.re) * hs, (z1.im - w1.im) * hs};
+                    *(float4 *)(Xh + cbase[cur][c] + l2) = o;
                 }
             }
         } else {

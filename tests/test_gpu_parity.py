@@ -241,7 +241,8 @@ def test_fit_est_matches_oracle(dtype):
 # mixing
 @pytest.mark.parametrize("dims,cdt", [((20, 30, 12), "c64"), ((50, 60, 7), "c64"), ((14, 9, 10, 8), "c128"),
                                       ((100, 90, 16), "c64"), ((400, 6, 150), "c64"), ((3, 1000, 5), "c64"),
-                                      ((60, 60, 60, 5), "c64")])
+                                      ((60, 60, 60, 5), "c64"), ((100, 9, 7), "c64"), ((400, 3, 7), "c64"),
+                                      ((128, 5, 5), "c64")])
 def test_mix_matches_oracle(dims, cdt):
     rng = _rng(12)
     X = rng.standard_normal(dims)
