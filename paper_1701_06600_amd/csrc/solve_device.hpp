@@ -145,31 +145,36 @@ __device__ inline double bsel(bool c, double a, double b) {
 // entirely in registers: the matrix is padded to 16 x 16 with zeros (the
 // padding is never a pivot and is left unchanged), lane l holds column
 // l % 16 of rows l / 16 + 4 q (q < 4), and each step fetches the pivot, the
-// pivot column and the pivot row from the owning lanes by shuffles.
-// Returns 1 if a pivot falls below 1e-12 maxdiag (B1 is then untouched).
+// pivot column and the pivot row from the owning lanes by shuffles, all six
+// issued together (none depends on another).  A pivot below 1e-12 maxdiag
+// is only recorded, so that no branch separates the fetches; the elimination
+// then runs on to the end on meaningless values.  Returns 1 if any pivot
+// failed (the same in every lane, as the pivots are broadcast).
 __device__ __forceinline__ int gj_wave_regs(double (&v)[4], int R, double maxdiag) {
     const int l = threadIdx.x & (kWave - 1), j = l & 15, i0 = l >> 4;
+    const double thr = 1e-12 * maxdiag;
+    int bad = 0;
     for (int k = 0; k < R; ++k) {
         const int kq = k >> 2;  // slot of row k (uniform)
         const double vk = kq == 0 ? v[0] : kq == 1 ? v[1] : kq == 2 ? v[2] : v[3];
         const double piv = __shfl(vk, ((k & 3) << 4) | k, kWave);
-        if (!(piv > 1e-12 * maxdiag)) return 1;  // uniform across the wave
-        const double inv = 1.0 / piv;
-        const double rowp = __shfl(vk, ((k & 3) << 4) | j, kWave) * inv;  // M(k, j) / M(k, k)
-        double c[4];  // pivot-column fetches, all issued before any is used
+        const double rk = __shfl(vk, ((k & 3) << 4) | j, kWave);  // M(k, j)
+        double c[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) c[q] = __shfl(v[q], (l & 48) | k, kWave);  // M(i0 + 4 q, k)
+        bad |= !(piv > thr);
+        const double inv = 1.0 / piv;
+        const double rowp = rk * inv;  // M(k, j) / M(k, k)
+        const double on_row = bsel(j == k, inv, rowp);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = i0 + 4 * q;
-            const double ci = c[q];
-            const double other = fma(-ci, rowp, v[q]);
-            const double on_col = -ci * inv;
-            const double on_row = bsel(j == k, inv, rowp);
+            const double other = fma(-c[q], rowp, v[q]);
+            const double on_col = -c[q] * inv;
             v[q] = bsel(i == k, on_row, bsel(j == k, on_col, other));
         }
     }
-    return 0;
+    return bad;
 }
 
 __device__ __forceinline__ int gj_wave(double *B1, int R, int ld, double maxdiag) {
