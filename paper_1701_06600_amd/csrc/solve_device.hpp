@@ -141,37 +141,84 @@ __device__ inline double bsel(bool c, double a, double b) {
     return __longlong_as_double((__double_as_longlong(a) & m) | (__double_as_longlong(b) & ~m));
 }
 
+// A double held by lane `lane` (a constant), as a wave-uniform value.
+__device__ __forceinline__ double read_lane(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// One scalar Gauss-Jordan step (pivot k) in the gj_wave_regs layout.
+__device__ __forceinline__ void gj_wave_step(double (&v)[4], int k, double thr, int &bad) {
+    const int l = threadIdx.x & (kWave - 1), j = l & 15, i0 = l >> 4;
+    const double vk = v[k >> 2];
+    const double piv = read_lane(vk, ((k & 3) << 4) | k);
+    const double rk = __shfl(vk, ((k & 3) << 4) | j, kWave);  // M(k, j)
+    double c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c[q] = __shfl(v[q], (l & 48) | k, kWave);  // M(i0 + 4 q, k)
+    bad |= !(piv > thr);
+    const double inv = 1.0 / piv;
+    const double rowp = rk * inv;  // M(k, j) / M(k, k)
+    const double on_row = bsel(j == k, inv, rowp);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = i0 + 4 * q;
+        v[q] = bsel(i == k, on_row, bsel(j == k, -c[q] * inv, fma(-c[q], rowp, v[q])));
+    }
+}
+
 // Gauss-Jordan elimination of B1 (R <= 16) by the first wavefront alone,
 // entirely in registers: the matrix is padded to 16 x 16 with zeros (the
-// padding is never a pivot and is left unchanged), lane l holds column
-// l % 16 of rows l / 16 + 4 q (q < 4), and each step fetches the pivot, the
-// pivot column and the pivot row from the owning lanes by shuffles, all six
-// issued together (none depends on another).  A pivot below 1e-12 maxdiag
-// is only recorded, so that no branch separates the fetches; the elimination
-// then runs on to the end on meaningless values.  Returns 1 if any pivot
-// failed (the same in every lane, as the pivots are broadcast).
+// padding is never a pivot and is left unchanged) and lane l holds column
+// l % 16 of rows l / 16 + 4 q (q < 4).  Pivots are taken two at a time,
+// K = {k, k+1} with P = M(K, K):
+//   M(K, K) <- P^{-1},  M(K, j) <- P^{-1} M(K, j),  M(i, K) <- -M(i, K) P^{-1},
+//   M(i, j) <- M(i, j) - M(i, K) P^{-1} M(K, j)      (i, j not in K),
+// which equals two scalar steps; P comes by lane reads (the lanes are
+// constants, the step loop being unrolled), the two pivot rows and columns by
+// shuffles all issued together, so a pair costs one round of exchanges.  The
+// scalar pivots M(k, k) and det P / M(k, k) are tested against 1e-12
+// maxdiag; a failure is only recorded (no branch between the exchanges) and
+// the elimination runs on to the end on meaningless values.  An odd last
+// pivot takes a scalar step.  Returns 1 if any pivot failed (the same in
+// every lane).
 __device__ __forceinline__ int gj_wave_regs(double (&v)[4], int R, double maxdiag) {
     const int l = threadIdx.x & (kWave - 1), j = l & 15, i0 = l >> 4;
     const double thr = 1e-12 * maxdiag;
     int bad = 0;
-    for (int k = 0; k < R; ++k) {
-        const int kq = k >> 2;  // slot of row k (uniform)
-        const double vk = kq == 0 ? v[0] : kq == 1 ? v[1] : kq == 2 ? v[2] : v[3];
-        const double piv = __shfl(vk, ((k & 3) << 4) | k, kWave);
-        const double rk = __shfl(vk, ((k & 3) << 4) | j, kWave);  // M(k, j)
-        double c[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) c[q] = __shfl(v[q], (l & 48) | k, kWave);  // M(i0 + 4 q, k)
-        bad |= !(piv > thr);
-        const double inv = 1.0 / piv;
-        const double rowp = rk * inv;  // M(k, j) / M(k, k)
-        const double on_row = bsel(j == k, inv, rowp);
+    for (int k = 0; k < 16; k += 2) {
+        if (k + 1 >= R) {
+            if (k < R) gj_wave_step(v, k, thr, bad);
+            break;
+        }
+        const int g0 = (k & 3) << 4, g1 = ((k + 1) & 3) << 4;  // lanes of rows k and k + 1
+        const double vk = v[k >> 2];                            // rows k and k + 1 share the slot
+        const double a = read_lane(vk, g0 | k), b = read_lane(vk, g0 | (k + 1));
+        const double c = read_lane(vk, g1 | k), d = read_lane(vk, g1 | (k + 1));
+        const double r0 = __shfl(vk, g0 | j, kWave), r1 = __shfl(vk, g1 | j, kWave);  // M(K, j)
+        double c0[4], c1[4];                                                          // M(i, K)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c0[q] = __shfl(v[q], (l & 48) | k, kWave);
+            c1[q] = __shfl(v[q], (l & 48) | (k + 1), kWave);
+        }
+        const double det = fma(a, d, -b * c);
+        bad |= !(a > thr) | !(det > thr * a);
+        const double id = 1.0 / det;
+        const double p00 = d * id, p01 = -b * id, p10 = -c * id, p11 = a * id;  // P^{-1}
+        const double s0 = fma(p00, r0, p01 * r1), s1 = fma(p10, r0, p11 * r1);  // P^{-1} M(K, j)
+        const bool jk0 = j == k, jk1 = j == k + 1;
+        const double on_row0 = bsel(jk0, p00, bsel(jk1, p01, s0));
+        const double on_row1 = bsel(jk0, p10, bsel(jk1, p11, s1));
+        const double e0 = bsel(jk0, p00, p01), e1 = bsel(jk0, p10, p11);  // column j of P^{-1}
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = i0 + 4 * q;
-            const double other = fma(-c[q], rowp, v[q]);
-            const double on_col = -c[q] * inv;
-            v[q] = bsel(i == k, on_row, bsel(j == k, on_col, other));
+            const double other = fma(-c0[q], s0, fma(-c1[q], s1, v[q]));
+            const double on_col = -fma(c0[q], e0, c1[q] * e1);
+            v[q] = bsel(i == k, on_row0, bsel(i == k + 1, on_row1, bsel(jk0 || jk1, on_col, other)));
         }
     }
     return bad;
@@ -197,15 +244,18 @@ __device__ __forceinline__ int gj_wave(double *B1, int R, int ld, double maxdiag
 // Gauss-Jordan inverse of B1, 16 < R <= C (C = 32 or 64), by the first four
 // waves in registers, zero-padded to C x C (padding rows and columns stay
 // zero).  Wave w holds rows w C/4 .. (w+1) C/4 - 1: lane l holds column
-// l % C of rows w C/4 + l / C + (64 / C) q.  Step k: the lanes holding row k
-// write it to rowbuf[(k & 1) C ..] (2 C doubles of LDS), one barrier, then
-// every thread reads M(k, k) and M(k, j) from there and takes M(i, k) of its
-// own rows from the lane of its own wave that holds column k, so a step costs
-// one barrier and no division on the owner's side.  The row loop is unrolled
-// over the slots of a lane so that row k's slot is a constant.  Returns 1 on
-// a pivot below 1e-12 maxdiag (the same value in every thread, so the whole
-// block leaves together; B1 is then untouched).  Every thread of the block
-// calls it (blockDim.x >= 256; further waves only meet the barriers).
+// l % C of rows w C/4 + l / C + (64 / C) q.  Pivots go two at a time with
+// the block update of gj_wave_regs: the lanes holding rows k and k + 1 (one
+// wave, as k is even and a wave holds an even number of rows) write them to
+// rowbuf (double-buffered, 4 C doubles of LDS), one barrier, then every
+// thread reads the 2 x 2 pivot block and its two row entries from there and
+// takes M(i, k), M(i, k + 1) of its own rows from the lanes of its own wave
+// that hold those columns (shuffles issued before the barrier).  An odd last
+// pivot takes a scalar step.  The row loop is unrolled over a wave's rows so
+// that the slots of the pivot rows are constants.  Returns 1 if a scalar
+// pivot falls below 1e-12 maxdiag (every thread reads the same pivots, so
+// all agree; B1 is then untouched).  Every thread of the block calls it
+// (blockDim.x >= 256; further waves only meet the barriers).
 template <int C>
 __device__ __forceinline__ int gj_rows(double *B1, double *rowbuf, int R, int ld, double maxdiag) {
     constexpr int H = kWave / C;  // row groups in a wave
@@ -215,6 +265,7 @@ __device__ __forceinline__ int gj_rows(double *B1, double *rowbuf, int R, int ld
     const int j = l % C, h = l / C, src = h * C;
     const bool act = w < 4;
     const double thr = 1e-12 * maxdiag;
+    int bad = 0;
     double v[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -223,33 +274,61 @@ __device__ __forceinline__ int gj_rows(double *B1, double *rowbuf, int R, int ld
     }
     for (int kw = 0; kw < 4; ++kw) {
 #pragma unroll
-        for (int kq = 0; kq < NQ; ++kq)
-#pragma unroll
-            for (int kh = 0; kh < H; ++kh) {
-                const int k = kw * RW + kh + H * kq;
-                if (k >= R) goto done;  // uniform
-                double *buf = rowbuf + (k & 1) * C;
-                if (w == kw && h == kh) buf[j] = v[kq];
-                double c[NQ];  // M(i, k) of this lane's rows, all issued before the barrier
+        for (int p = 0; p < RW / 2; ++p) {
+            const int k = kw * RW + 2 * p;
+            if (k >= R) goto done;  // uniform
+            const int kh0 = (2 * p) % H, kq0 = (2 * p) / H, kh1 = (2 * p + 1) % H, kq1 = (2 * p + 1) / H;
+            double *buf = rowbuf + (p & 1) * 2 * C;  // consecutive pairs alternate
+            if (k + 1 >= R) {  // odd R: the last pivot alone
+                if (w == kw && h == kh0) buf[j] = v[kq0];
+                double c[NQ];
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) c[q] = __shfl(v[q], src + k, kWave);
                 __syncthreads();
-                const double piv = buf[k];
-                const double rk = buf[j];
-                if (!(piv > thr)) return 1;
+                const double piv = buf[k], rk = buf[j];
+                bad |= !(piv > thr);
                 const double inv = 1.0 / piv;
-                const double rowp = rk * inv;  // M(k, j) / M(k, k)
+                const double rowp = rk * inv;
                 const double on_row = bsel(j == k, inv, rowp);
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
-                    const double other = fma(-c[q], rowp, v[q]);
-                    const double on_col = -c[q] * inv;
-                    const bool rowk = (q == kq) && (w == kw) && (h == kh);
-                    v[q] = bsel(rowk, on_row, bsel(j == k, on_col, other));
+                    const bool rowk = (q == kq0) && (w == kw) && (h == kh0);
+                    v[q] = bsel(rowk, on_row, bsel(j == k, -c[q] * inv, fma(-c[q], rowp, v[q])));
                 }
+                goto done;
             }
+            if (w == kw && h == kh0) buf[j] = v[kq0];
+            if (w == kw && h == kh1) buf[C + j] = v[kq1];
+            double c0[NQ], c1[NQ];  // M(i, k), M(i, k + 1) of this lane's rows
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                c0[q] = __shfl(v[q], src + k, kWave);
+                c1[q] = __shfl(v[q], src + k + 1, kWave);
+            }
+            __syncthreads();
+            const double a = buf[k], b = buf[k + 1], c = buf[C + k], d = buf[C + k + 1];
+            const double r0 = buf[j], r1 = buf[C + j];
+            const double det = fma(a, d, -b * c);
+            bad |= !(a > thr) | !(det > thr * a);
+            const double id = 1.0 / det;
+            const double p00 = d * id, p01 = -b * id, p10 = -c * id, p11 = a * id;
+            const double s0 = fma(p00, r0, p01 * r1), s1 = fma(p10, r0, p11 * r1);
+            const bool jk0 = j == k, jk1 = j == k + 1;
+            const double on_row0 = bsel(jk0, p00, bsel(jk1, p01, s0));
+            const double on_row1 = bsel(jk0, p10, bsel(jk1, p11, s1));
+            const double e0 = bsel(jk0, p00, p01), e1 = bsel(jk0, p10, p11);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const bool rowk0 = (q == kq0) && (w == kw) && (h == kh0);
+                const bool rowk1 = (q == kq1) && (w == kw) && (h == kh1);
+                const double other = fma(-c0[q], s0, fma(-c1[q], s1, v[q]));
+                const double on_col = -fma(c0[q], e0, c1[q] * e1);
+                v[q] = bsel(rowk0, on_row0, bsel(rowk1, on_row1, bsel(jk0 || jk1, on_col, other)));
+            }
+        }
     }
 done:
+    if (bad) return 1;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int i = w * RW + h + H * q;
@@ -265,18 +344,22 @@ done:
 // failed pivot); B1 is then not written.  No barrier inside.
 __device__ __forceinline__ int gj_wave_from_regs(double (&v)[4], double *B1, double *B3, int R, int ld) {
     const int l = threadIdx.x & (kWave - 1), j = l & 15, i0 = l >> 4;
-    double d = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int i = i0 + 4 * q;
         if (i < R && j < R) B3[i * ld + j] = v[q];
-        if (i == j && i < R) d = v[q];
     }
-    const int nf = !isfinite(d);
-    double mx = fabs(d);
+    // the diagonal by lane reads (wave-uniform values, no exchange rounds)
+    double mx = 0.0;
+    bool nf = false;
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
-    if (__any(nf) || !(mx > 0.0)) return 1;
+    for (int i = 0; i < 16; ++i) {
+        if (i >= R) break;
+        const double d = read_lane(v[i >> 2], ((i & 3) << 4) | i);
+        nf = nf || !isfinite(d);
+        mx = fmax(mx, fabs(d));
+    }
+    if (nf || !(mx > 0.0)) return 1;
     if (gj_wave_regs(v, R, mx)) return 1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {

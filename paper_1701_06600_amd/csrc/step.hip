@@ -23,6 +23,16 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kStepThreads = 512;
 constexpr int kColParts = 16;
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+    typedef float2 type;
+};
+template <>
+struct Pair<double> {
+    typedef double2 type;
+};
 constexpr int kMaxParts = 8;  // partial products summed here (the gathers use at most this many chunks)
 constexpr int kMixGroups = 3; // mixed products: (column, VL rows) groups per thread per pass, loads in flight together
 static_assert(kColParts * kMaxRank >= kStepThreads, "tmp holds one double per thread");
@@ -306,6 +316,7 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
                 for (int w = 0; w < nw; ++w) s += tmp[w * 16 + tid];
                 const double l = sqrt(s);
                 B2[tid] = l;
+                B2[R + tid] = l > 0.0 ? 1.0 / l : 1.0;  // B2 holds R (R + 1) >= 2 R doubles
                 a.lambda[tid] = l;
                 if (a.snap_lambda) a.snap_lambda[tid] = l;
             }
@@ -343,22 +354,22 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
                 for (int k0 = 0; k0 < kstride; ++k0) s += tmp[k0 * R + tid];
                 const double l = sqrt(s);
                 B2[tid] = l;
+                B2[R + tid] = l > 0.0 ? 1.0 / l : 1.0;  // B2 holds R (R + 1) >= 2 R doubles
                 a.lambda[tid] = l;
                 if (a.snap_lambda) a.snap_lambda[tid] = l;
             }
             __syncthreads();
         }
-        T *Ah = (T *)a.Ahat;
+        typedef typename Pair<T>::type P2;  // one complex entry per store
+        P2 *Ah = (P2 *)a.Ahat;
+        P2 *Sn = (P2 *)a.snapA;
         for (int e = tid; e < In * R; e += kStepThreads) {
-            const double l = B2[e % R];
-            const double q = l > 0.0 ? 1.0 / l : 1.0;
-            const T re = (T)(Ad[e] * q), im = (T)(Ai[e] * q);
-            Ah[2 * (size_t)e] = re;
-            Ah[2 * (size_t)e + 1] = im;
-            if (a.snapA) {
-                ((T *)a.snapA)[2 * (size_t)e] = re;
-                ((T *)a.snapA)[2 * (size_t)e + 1] = im;
-            }
+            const double q = B2[R + e % R];
+            P2 z;
+            z.x = (T)(Ad[e] * q);
+            z.y = (T)(Ai[e] * q);
+            Ah[e] = z;
+            if (Sn) Sn[e] = z;
         }
         return;
     }
@@ -408,16 +419,14 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
         for (int part = 0; part < kColParts; ++part) s += tmp[tid * kColParts + part];
         const double l = sqrt(s);
         B2[tid] = l;  // B2 is free after the inversion
+        B2[R + tid] = l > 0.0 ? 1.0 / l : 1.0;
         a.lambda[tid] = l;
         if (a.snap_lambda) a.snap_lambda[tid] = l;
     }
     __syncthreads();
     T *A = (T *)a.A;
     for (int e = tid; e < In * R; e += kStepThreads) {
-        const int r = e % R;
-        const double l = B2[r];
-        const T v = (T)Ad[e];
-        const T nv = l > 0.0 ? (T)((double)v / l) : v;
+        const T nv = (T)((double)(T)Ad[e] * B2[R + e % R]);
         A[e] = nv;
         if (a.snapA) ((T *)a.snapA)[e] = nv;
     }

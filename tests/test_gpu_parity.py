@@ -175,7 +175,7 @@ def test_solve_matches_numpy(In, R):
     assert int(info.item()) == 0
 
 
-@pytest.mark.parametrize("R,rk", [(6, 4), (24, 12), (40, 30)])
+@pytest.mark.parametrize("R,rk", [(6, 4), (6, 5), (7, 6), (24, 12), (40, 30)])
 def test_solve_singular_uses_pseudoinverse(R, rk):
     rng = _rng(3 + R)
     Z = rng.standard_normal((rk, R))         # rank rk < R
