@@ -157,6 +157,13 @@ __global__ __launch_bounds__(NT) void mix_pass_ct(const Tin *X, cx<float> *Xh, i
     }
 }
 
+// Non-temporal 16-byte store (the written tensor is not read again before it
+// has left the caches).
+typedef float ntv4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_nt(void *p, float4 v) {
+    __builtin_nontemporal_store(ntv4{v.x, v.y, v.z, v.w}, (ntv4 *)p);
+}
+
 // Software-pipelined form of the 16-byte passes above for long tensors: a
 // persistent grid (a few workgroups per CU) walks the tiles t = blockIdx.x,
 // blockIdx.x + gridDim.x, ...; the global loads of the next tile are issued
@@ -166,7 +173,8 @@ __global__ __launch_bounds__(NT) void mix_pass_ct(const Tin *X, cx<float> *Xh, i
 // z = x + i y, and splits the result by conjugate symmetry:
 //   X(k) = (Z(k) + conj Z(L-k)) / 2,  Y(k) = (Z(k) - conj Z(L-k)) / (2 i),
 // so a tile holds 2 TC fibers and the FFT work per element halves.  Other
-// passes: same arithmetic and output as mix_pass_ct.
+// passes: same arithmetic and output as mix_pass_ct, with non-temporal stores
+// (measured faster for these passes, slower for the first).
 template <int L, int TC, int NT, bool FIRST>
 __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *Xh, int64_t J, int64_t K, ModeInfo xi,
                                                     int m, const int8_t *signs, const cx<float> *twg,
@@ -341,8 +349,8 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
                 const int l = e / (TC / 2), c = (e - l * (TC / 2)) * 2;
                 if (c < nc) {
                     const cx<float> a = buf[l * LDT + c], b = buf[l * LDT + c + 1];
-                    *(float4 *)(Xh + cbase[cur][c] + J * (int64_t)l) = {a.re * scale, a.im * scale, b.re * scale,
-                                                                       b.im * scale};
+                    store_nt(Xh + cbase[cur][c] + J * (int64_t)l, float4{a.re * scale, a.im * scale, b.re * scale,
+                                                                       b.im * scale});
                 }
             }
             if (copy) {  // the same fibers again, each stored contiguously (fiber q at copy + q * L)
@@ -350,8 +358,8 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
                     const int c = e / (L / 2), l2 = (e - c * (L / 2)) * 2;
                     if (c < nc) {
                         const cx<float> a = buf[l2 * LDT + c], b = buf[(l2 + 1) * LDT + c];
-                        *(float4 *)(copy + (t * TC + c) * (int64_t)L + l2) = {a.re * scale, a.im * scale,
-                                                                             b.re * scale, b.im * scale};
+                        store_nt(copy + (t * TC + c) * (int64_t)L + l2, float4{a.re * scale, a.im * scale,
+                                                                             b.re * scale, b.im * scale});
                     }
                 }
             }
