@@ -170,12 +170,41 @@ __device__ inline float mlp_row(const float *P, const float x[4]) {
     return z;
 }
 
+// The network's output without its bias, restricted to second-layer units
+// j = q, q + 4, ... (q < 4); the four parts sum to mlp_row(P, x) - b3.  W2p
+// holds the second-layer weights with rows padded to kH1 + 1 floats, so the
+// four lanes of a quad (four rows j) read different LDS banks.
+__device__ inline float mlp_part(const float *P, const float *W2p, const float x[4], int q) {
+    float h1[kH1];
+#pragma unroll
+    for (int j = 0; j < kH1; ++j) {
+        float s = P[kOffB1 + j];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) s += P[kOffW1 + j * kIn + k] * x[k];
+        h1[j] = s > 0.f ? s : 0.f;
+    }
+    float z = 0.f;
+    for (int j = q; j < kH2; j += 4) {
+        float w[kH1];  // the unit's weights, all reads issued before the sums
+#pragma unroll
+        for (int k = 0; k < kH1; ++k) w[k] = W2p[j * (kH1 + 1) + k];
+        float s4[4] = {P[kOffB2 + j], 0.f, 0.f, 0.f};  // four independent chains
+#pragma unroll
+        for (int k = 0; k < kH1; ++k) s4[k & 3] += w[k] * h1[k];
+        const float s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+        z += P[kOffW3 + j] * (s > 0.f ? s : 0.f);
+    }
+    return z;
+}
+
 // Row scores for every mode m != n: mode == LEARNED: the network's logit;
 // mode == MARGINAL: log of the exact marginal.  Also (optionally) writes the
-// feature rows and the exact targets L/R for training.  One wave per
-// kScoreRows rows: G^{-1}, the marginal matrix H_m = Hinv * prod_{k in
-// K\{m}} G_k (Hadamard products), the rows (transposed) and the network
-// are staged in LDS, and each lane evaluates the quadratic forms of its row.
+// feature rows and the exact targets L/R for training.  One workgroup of
+// four waves per kScoreRows rows: G^{-1}, the marginal matrix H_m = Hinv *
+// prod_{k in K\{m}} G_k (Hadamard products), the rows (transposed) and the
+// network are staged in LDS; the quadratic forms run on FP64 MFMA over
+// 16-row blocks shared by the waves, one thread per row forms the features,
+// and four lanes per row evaluate the network.
 struct RowArgs {
     FactorPtrs A;
     ModeInfo mi;
@@ -190,7 +219,7 @@ struct RowArgs {
     int64_t row_off[kMaxOrder];  // first row of mode m in feat/target
 };
 
-constexpr int kScoreRows = 128, kScoreThreads = 128;
+constexpr int kScoreRows = 128, kScoreThreads = 256;
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 
 __host__ __device__ inline int pad16(int R) { return (R + 15) & ~15; }
@@ -198,20 +227,19 @@ __host__ __device__ inline int pad16(int R) { return (R + 15) & ~15; }
 size_t row_scores_lds(int R, bool marg, bool learned) {
     const size_t RP = pad16(R);
     size_t b = sizeof(double) * (RP * RP * (marg ? 2 : 1) + R + 2 * kScoreRows) + sizeof(float) * RP * kScoreRows;
-    if (learned) b += sizeof(float) * kParams;
+    if (learned) b += sizeof(float) * (kParams + 4 * kScoreRows + kH2 * (kH1 + 1));
     return b;
 }
 
 // Quadratic forms q_i = a_i^T M a_i for the block's rows: U = A_rows M on
 // FP64 MFMA 16x16x4 (lane l: A operand A[l%16][l/16], B operand
 // M[l/16][l%16], result U[l/16 + 4v][l%16]), then the row sums of U * A by
-// shuffles over the 16 lanes that share a row, in a fixed order.
+// shuffles over the 16 lanes that share a row, in a fixed order.  The
+// 16-row blocks go round-robin over the waves of the block.
 __device__ inline void quad_forms(const float *sRow, const double *M1, const double *M2, int RP, int nr, double *q1,
                                   double *q2) {
     const int w = threadIdx.x / kWave, l = threadIdx.x & (kWave - 1), li = l & 15, lk = l >> 4;
-    for (int rt = 0; rt < 4; ++rt) {
-        const int rb = w * 64 + rt * 16;
-        if (rb >= nr) break;
+    for (int rb = w * 16; rb < nr; rb += (kScoreThreads / kWave) * 16) {
         double p1[4] = {0.0, 0.0, 0.0, 0.0}, p2[4] = {0.0, 0.0, 0.0, 0.0};
         for (int ct = 0; ct < RP; ct += 16) {
             v4d_t u1 = {0.0, 0.0, 0.0, 0.0}, u2 = {0.0, 0.0, 0.0, 0.0};
@@ -276,8 +304,20 @@ __global__ __launch_bounds__(kScoreThreads) void row_scores_kernel(RowArgs a) {
         }
     }
     for (int r = tid; r < R; r += kScoreThreads) sGd[r] = G[r * R + r];
-    if (a.learned)
-        for (int e = tid; e < kParams; e += kScoreThreads) P[e] = a.params[e];
+    if (a.learned) {
+        constexpr int PU = (kParams + kScoreThreads - 1) / kScoreThreads;
+        float t[PU];  // every load of this thread in flight before the first store
+#pragma unroll
+        for (int u = 0; u < PU; ++u) t[u] = a.params[min(tid + u * kScoreThreads, kParams - 1)];
+        float *W2p = P + kParams + 4 * kScoreRows;  // second-layer weights, rows padded to kH1 + 1
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const int e = tid + u * kScoreThreads;
+            if (e < kParams) P[e] = t[u];
+            const int w = e - kOffW2;
+            if (w >= 0 && w < kH2 * kH1) W2p[(w / kH1) * (kH1 + 1) + w % kH1] = t[u];
+        }
+    }
     const int nr = (int)min((int64_t)kScoreRows, I - r0);
     for (int e = tid; e < RP * kScoreRows; e += kScoreThreads) sRow[e] = 0.f;
     __syncthreads();
@@ -297,32 +337,53 @@ __global__ __launch_bounds__(kScoreThreads) void row_scores_kernel(RowArgs a) {
     __syncthreads();
     quad_forms(sRow, sGi, marg ? sH : nullptr, RP, nr, sLev, sMg);
     __syncthreads();
-    if (tid >= nr) return;
-    const int64_t i = r0 + tid;
-    const double frob2 = G[2 * R * R];
-    double rn = 0.0, cn = 0.0;
-    for (int r = 0; r < R; ++r) {
-        const double ar = (double)sRow[r * kScoreRows + tid];
-        rn += ar * ar;
-        cn += ar * ar / sGd[r];
+    float *sX = P + kParams;  // [kScoreRows][4] features (learned)
+    if (tid < nr) {
+        const int64_t i = r0 + tid;
+        const double frob2 = G[2 * R * R];
+        double rn = 0.0, cn = 0.0;
+        for (int r = 0; r < R; ++r) {
+            const double ar = (double)sRow[r * kScoreRows + tid];
+            rn += ar * ar;
+            cn += ar * ar / sGd[r];
+        }
+        const double lev = sLev[tid], mg = marg ? sMg[tid] : 0.0;
+        const double f1 = (double)I * rn / frob2, f2 = (double)I / R * lev, f3 = (double)I / R * cn;
+        const float x[4] = {logf((float)f1 + kFeatEps), logf((float)f2 + kFeatEps), logf((float)f3 + kFeatEps),
+                            (float)f4};
+        if (a.learned) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sX[tid * 4 + k] = x[k];
+        } else if (a.score[m]) {
+            a.score[m][i] = logf((float)fmax(mg, 1e-30));
+        }
+        if (a.feat) {
+            float *f = a.feat + (a.row_off[m] + i) * 4;
+            f[0] = x[0];
+            f[1] = x[1];
+            f[2] = x[2];
+            f[3] = x[3];
+        }
+        if (a.target) a.target[a.row_off[m] + i] = (float)(mg / R);
     }
-    const double lev = sLev[tid], mg = marg ? sMg[tid] : 0.0;
-    const double f1 = (double)I * rn / frob2, f2 = (double)I / R * lev, f3 = (double)I / R * cn;
-    float x[4] = {logf((float)f1 + kFeatEps), logf((float)f2 + kFeatEps), logf((float)f3 + kFeatEps), (float)f4};
-    float sc;
-    if (a.learned)
-        sc = mlp_row(P, x);
-    else
-        sc = logf((float)fmax(mg, 1e-30));
-    if (a.score[m]) a.score[m][i] = sc;
-    if (a.feat) {
-        float *f = a.feat + (a.row_off[m] + i) * 4;
-        f[0] = x[0];
-        f[1] = x[1];
-        f[2] = x[2];
-        f[3] = x[3];
+    if (!a.learned) return;
+    __syncthreads();
+    // the network, four lanes per row: each lane the first layer whole and a
+    // quarter of the second-layer units with their output terms, summed over
+    // the quad
+    const int sub = tid & 3;
+    for (int row = tid >> 2; row < nr; row += kScoreThreads / 4) {
+        // keeps the compiler from hoisting the weight reads out of the row
+        // loop (holding them would leave no registers for the inner loads)
+        asm volatile("" ::: "memory");
+        float x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = sX[row * 4 + k];
+        float z = mlp_part(P, P + kParams + 4 * kScoreRows, x, sub);
+        z += __shfl_xor(z, 1, kWave);
+        z += __shfl_xor(z, 2, kWave);
+        if (sub == 0 && a.score[m]) a.score[m][r0 + row] = z + P[kOffB3];
     }
-    if (a.target) a.target[a.row_off[m] + i] = (float)(mg / R);
 }
 
 // Per mode m != n: p = softmax(score), mixture (1-alpha) p + alpha/I,
