@@ -56,6 +56,7 @@ struct View {
     int kind = 0;
     int64_t strides[CPRAND_MAX_ORDER] = {};
     int64_t ld = 0;
+    bool contig = true;     // with data: fibers along the view's mode are unit-stride
 };
 
 struct cprand_plan {
@@ -253,14 +254,14 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         // the whole post-gather step in one workgroup when it fits in LDS
         bool fused = step_finish_lds((int32_t)In, R, p->mix) <= 156 * 1024;
         const bool rcontig = p->refine && (p->rview[n].data ? true : contig_x[n]);
-        GatherPlan gp = plan_gather(p->gkind, R, p->o.S, In, v.data ? true : contig_x[n],
+        GatherPlan gp = plan_gather(p->gkind, R, p->o.S, In, v.data ? v.contig : contig_x[n],
                                     fused ? kChunksFused : kChunksSplit);
         GatherPlan gr = p->refine ? plan_gather(K_F32, R, p->o.S, In, rcontig, fused ? kChunksFused : kChunksSplit)
                                   : GatherPlan{};
         if (fused && (gp.chunks > kChunksFused || (p->refine && gr.chunks > kChunksFused))) {
             // the LDS limit shrank the chunks: too many partials for the fused step
             fused = false;
-            gp = plan_gather(p->gkind, R, p->o.S, In, v.data ? true : contig_x[n], kChunksSplit);
+            gp = plan_gather(p->gkind, R, p->o.S, In, v.data ? v.contig : contig_x[n], kChunksSplit);
             if (p->refine) gr = plan_gather(K_F32, R, p->o.S, In, rcontig, kChunksSplit);
         }
         GatherArgs ga{};
@@ -549,8 +550,17 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     } else {
         for (int n = 0; n < N && e == hipSuccess; ++n) {
             if (p->bf16) {
-                e = alloc_copy(p->gview[n], K_BF16, n);
-                if (e != hipSuccess) break;
+                if (o.layout == 1 && n > 0) {
+                    // strided BF16 gathers from the mode-0 copy: one conversion of X
+                    // instead of a mode-major copy per mode
+                    View &v = p->gview[n];
+                    v = p->gview[0];
+                    v.own = false;
+                    v.contig = false;
+                } else {
+                    e = alloc_copy(p->gview[n], K_BF16, n);
+                    if (e != hipSuccess) break;
+                }
             }
             View &v = p->bf16 ? p->rview[n] : p->gview[n];
             if (p->bf16 && !p->refine) continue;

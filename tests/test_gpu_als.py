@@ -87,15 +87,18 @@ def test_cprand_mix_f64_tracks_oracle(use_graph):
         assert np.allclose(a, b, atol=1e-7)
 
 
-def test_cprand_bf16_refined_reaches_fp64_fit():
+@pytest.mark.parametrize("layout", [0, 1])
+def test_cprand_bf16_refined_reaches_fp64_fit(layout):
+    """layout 0: BF16 and FP32 mode-major copies; layout 1: strided gathers
+    from one BF16 conversion of X and from X itself."""
     p = synth.make_problem((40, 36, 32, 28), 5, congruence=0.5, noise=0.01, seed=9)
     X = synth.dense_tensor(p).astype(np.float32).astype(np.float64)
     S = 200
-    out, A = _run_gpu(X, p.init, 5, S, 4, torch.float32, max_iters=60, precision=P.PREC_BF16_REFINE)
+    out, A = _run_gpu(X, p.init, 5, S, 4, torch.float32, max_iters=60, precision=P.PREC_BF16_REFINE, layout=layout)
     lam_r, A_r, _ = OC.cprand(X, 5, S, p.init, 4, 60)
     F = OC.exact_fit(X, out["lambda"].cpu().numpy(), A)
     assert abs(F - OC.exact_fit(X, lam_r, A_r)) < 1e-3
-    out2, A2 = _run_gpu(X, p.init, 5, S, 4, torch.float32, max_iters=60, precision=P.PREC_BF16)
+    out2, A2 = _run_gpu(X, p.init, 5, S, 4, torch.float32, max_iters=60, precision=P.PREC_BF16, layout=layout)
     F2 = OC.exact_fit(X, out2["lambda"].cpu().numpy(), A2)
     assert abs(F2 - OC.exact_fit(X, lam_r, A_r)) < 1e-3
 
