@@ -113,6 +113,8 @@ struct cprand_plan {
     std::vector<void *> allocs;
     hipStream_t cap = nullptr;
     hipStream_t fst = nullptr;       // the fit estimates of the direct-launch loop
+    hipStream_t rst = nullptr;       // the FP32 refinement gathers, beside the BF16 gathers
+    hipEvent_t ev_ref[2] = {};       // refinement gather: fork, join
     hipEvent_t ev_state[2] = {};     // iteration state complete (parity of t)
     hipEvent_t ev[4] = {};
     // setup timing: [0,1] norm, [2+2m, 3+2m] mix pass m, [2+2N+2m, 3+2N+2m] layout copy m
@@ -122,6 +124,9 @@ struct cprand_plan {
         if (hist_host) (void)hipHostFree(hist_host);
         if (cap) (void)hipStreamDestroy(cap);
         if (fst) (void)hipStreamDestroy(fst);
+        if (rst) (void)hipStreamDestroy(rst);
+        for (auto &e : ev_ref)
+            if (e) (void)hipEventDestroy(e);
         for (auto &e : ev_state)
             if (e) (void)hipEventDestroy(e);
         for (auto &e : ev)
@@ -314,16 +319,22 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         }
         ga.wpart = p->wpart;
         ga.vpart = p->vpart;
-        e = launch_gather(gp, ga, st);
-        if (e == hipSuccess && p->refine) {
+        if (p->refine) {
+            // the FP32 refinement gather (same samples, its own partials) on a
+            // second stream, forked before and joined after the BF16 gather
             const View &rv = p->rview[n];
             GatherArgs g2 = ga;
             for (int m = 0; m < N; ++m) g2.mi.strides[m] = rv.strides[m];
             g2.X = view_ptr(p, rv, xdata);
             g2.wpart = p->rpart;
             g2.vpart = p->vrpart;
-            e = launch_gather(gr, g2, st);
+            e = hipEventRecord(p->ev_ref[0], st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(p->rst, p->ev_ref[0], 0);
+            if (e == hipSuccess) e = launch_gather(gr, g2, p->rst);
+            if (e == hipSuccess) e = hipEventRecord(p->ev_ref[1], p->rst);
         }
+        if (e == hipSuccess) e = launch_gather(gp, ga, st);
+        if (e == hipSuccess && p->refine) e = hipStreamWaitEvent(st, p->ev_ref[1], 0);
         if (e != hipSuccess) break;
         if (fused) {
             StepArgs sa{};
@@ -667,6 +678,9 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&p->hist_mapped, p->hist_host, 0);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->fst, hipStreamNonBlocking);
+    if (e == hipSuccess && p->refine) e = hipStreamCreateWithFlags(&p->rst, hipStreamNonBlocking);
+    for (int i = 0; i < 2 && e == hipSuccess && p->refine; ++i)
+        e = hipEventCreateWithFlags(&p->ev_ref[i], hipEventDisableTiming);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&p->ev_state[i], hipEventDisableTiming);
     for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&p->ev[i]);
     for (int i = 0; i < 2 + 4 * CPRAND_MAX_ORDER && e == hipSuccess; ++i) e = hipEventCreate(&p->tev[i]);
