@@ -254,22 +254,27 @@ def precision_leg(P, synth, torch, dev, reps):
     Xv = P.View(X, w.dims)
     init = [torch.as_tensor(M, dtype=torch.float32, device=dev) for M in prob.init]
     res = {}
-    for name, prec in (("fp32", P.PREC_NATIVE), ("bf16_refine", P.PREC_BF16_REFINE)):
-        opts = P.make_opts(w.R, w.S, P_hat=w.P_hat, max_iters=w.max_iters, seed=w.seed, tol=w.tol,
-                           fit_target=w.fit_target, precision=prec, layout=0, use_graph=0)
-        plan = P.Plan(Xv, opts)
-        r, sec = _timed_runs(plan, Xv, init, reps)
-        plan.close()
-        res[name] = {"iters": r["iters"], "s_per_decomposition": sec, "iters_per_s": r["iters"] / sec,
-                     "loop_iters_per_s": r["iters"] / (r["loop_ms"] * 1e-3), "setup_ms": r["setup_ms"],
-                     "final_fit_est": r["fit_est"]}
-        print("[bench] precision %s: %d iters, %.3f s, F-hat %.5f" % (name, r["iters"], sec, r["fit_est"]),
-              flush=True)
-    d = abs(res["bf16_refine"]["final_fit_est"] - res["fp32"]["final_fit_est"])
+    # layout 0: mode-major copies of every mode (FP32, and BF16 for the BF16
+    # form); layout 1: strided gathers from X (the BF16 form from one BF16
+    # conversion of X)
+    for layout, key in ((0, None), (1, "strided")):
+        out = res if key is None else res.setdefault(key, {})
+        for name, prec in (("fp32", P.PREC_NATIVE), ("bf16_refine", P.PREC_BF16_REFINE)):
+            opts = P.make_opts(w.R, w.S, P_hat=w.P_hat, max_iters=w.max_iters, seed=w.seed, tol=w.tol,
+                               fit_target=w.fit_target, precision=prec, layout=layout, use_graph=0)
+            plan = P.Plan(Xv, opts)
+            r, sec = _timed_runs(plan, Xv, init, reps)
+            plan.close()
+            out[name] = {"iters": r["iters"], "s_per_decomposition": sec, "iters_per_s": r["iters"] / sec,
+                         "loop_iters_per_s": r["iters"] / (r["loop_ms"] * 1e-3), "setup_ms": r["setup_ms"],
+                         "final_fit_est": r["fit_est"]}
+            print("[bench] precision %s layout %d: %d iters, %.3f s, F-hat %.5f"
+                  % (name, layout, r["iters"], sec, r["fit_est"]), flush=True)
+        d = abs(out["bf16_refine"]["final_fit_est"] - out["fp32"]["final_fit_est"])
+        out["equal_fit"] = d <= 1e-3
+        out["fit_diff"] = d
+        out["speedup_per_decomposition"] = out["fp32"]["s_per_decomposition"] / out["bf16_refine"]["s_per_decomposition"]
     res["workload"] = "150x150x150x150, R=20, congruence 0.5, 1% noise, S=1000, paper stop rule"
-    res["equal_fit"] = d <= 1e-3
-    res["fit_diff"] = d
-    res["speedup_per_decomposition"] = res["fp32"]["s_per_decomposition"] / res["bf16_refine"]["s_per_decomposition"]
     return res
 
 
