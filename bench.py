@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 # same counters read for a 1 GiB device copy (FETCH_SIZE x 2, WRITE_SIZE x 1).
 # Valid for the kernel as measured; None when the mixing kernel has changed
 # since the counters were taken.
-MIX_TRAFFIC_BYTES = (2 * 125132 + 500008 + 2 * 250080 + 500000 + 2 * 250082 + 1000000) * 1024 / 3
+MIX_TRAFFIC_BYTES = (2 * 125134 + 500009 + 2 * 250085 + 500013 + 2 * 250082 + 1000474) * 1024 / 3
 # the same 1 GiB copy (read + write) took 423 us: 5.08 TB/s, the practical ceiling seen
 COPY_GBPS = 2 * 1073741824 / 423e-6 / 1e9
 
