@@ -529,11 +529,10 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *params, cons
     if (tid < nr) {
         const int64_t i = r0 + tid;
         float x[4] = {X[i * 4], X[i * 4 + 1], X[i * 4 + 2], X[i * 4 + 3]};
-        float a1[kH1], h1[kH1];
+        float h1[kH1];  // relu(a1); a1 > 0 exactly where h1 > 0
         for (int j = 0; j < kH1; ++j) {
             float s = P[kOffB1 + j];
             for (int k = 0; k < kIn; ++k) s += P[kOffW1 + j * kIn + k] * x[k];
-            a1[j] = s;
             h1[j] = s > 0.f ? s : 0.f;
             sh1[tid][j] = h1[j];
         }
@@ -541,14 +540,19 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *params, cons
         float dh1[kH1];
         for (int k = 0; k < kH1; ++k) dh1[k] = 0.f;
         for (int j = 0; j < kH2; ++j) {
+            float w[kH1];  // row j of W2, read once (all reads issued together) for both products
+#pragma unroll
+            for (int k = 0; k < kH1; ++k) w[k] = P[kOffW2 + j * kH1 + k];
             float s = P[kOffB2 + j];
-            for (int k = 0; k < kH1; ++k) s += P[kOffW2 + j * kH1 + k] * h1[k];
+#pragma unroll
+            for (int k = 0; k < kH1; ++k) s += w[k] * h1[k];
             sh2[tid][j] = s > 0.f ? s : 0.f;
             const float d2 = s > 0.f ? d * P[kOffW3 + j] : 0.f;
             sd2[tid][j] = d2;
-            for (int k = 0; k < kH1; ++k) dh1[k] += d2 * P[kOffW2 + j * kH1 + k];
+#pragma unroll
+            for (int k = 0; k < kH1; ++k) dh1[k] += d2 * w[k];
         }
-        for (int k = 0; k < kH1; ++k) sd1[tid][k] = a1[k] > 0.f ? dh1[k] : 0.f;
+        for (int k = 0; k < kH1; ++k) sd1[tid][k] = h1[k] > 0.f ? dh1[k] : 0.f;
         for (int k = 0; k < kIn; ++k) sx[tid][k] = x[k];
         sdz[tid] = d;
     }
@@ -578,6 +582,18 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *params, cons
     }
 }
 
+// The per-block gradients summed in two fixed-order stages.  Stage one,
+// chunk c = blockIdx.y < nchunks: the parts b = c, c + nchunks, ... of
+// parameter p, written in place over part c (which only this thread reads).
+__global__ __launch_bounds__(256) void grad_chunk_kernel(float *gpart, int32_t nparts, int32_t nchunks) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+    if (p >= kParams || c >= nchunks) return;
+    double acc = 0.0;
+    for (int b = c; b < nparts; b += nchunks) acc += (double)gpart[(size_t)b * kParams + p];
+    gpart[(size_t)c * kParams + p] = (float)acc;
+}
+
+// Stage two: the nchunks chunk sums in order.
 __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *gpart, int32_t nparts, float *grad) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= kParams) return;
@@ -669,7 +685,10 @@ hipError_t launch_mlp_grad(const float *params, const float *X, const float *dz,
                            float *grad, hipStream_t st) {
     const int nb = mlp_grad_blocks(rows);
     hipLaunchKernelGGL(mlp_grad_kernel, dim3(nb), dim3(256), 0, st, params, X, dz, rows, gpart);
-    hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)ceil_div(kParams, 256)), dim3(256), 0, st, gpart, nb, grad);
+    const int nchunks = std::min(nb, 64);  // stage one reads nb parts, writes parts 0 .. nchunks-1
+    const unsigned pb = (unsigned)ceil_div(kParams, 256);
+    hipLaunchKernelGGL(grad_chunk_kernel, dim3(pb, nchunks), dim3(256), 0, st, gpart, nb, nchunks);
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3(pb), dim3(256), 0, st, gpart, nchunks, grad);
     return hipGetLastError();
 }
 
