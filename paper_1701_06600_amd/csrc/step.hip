@@ -78,10 +78,10 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
         B1[i * ld + j] = acc;
         B3[i * ld + j] = acc;
     };
-    // R <= 16: wave 0 loads V in the register layout of the one-wave
-    // Gauss-Jordan inverse and inverts it while the other waves load and sum
-    // the product partials; larger R: Gram element tid is loaded here and
-    // summed after the product loads have been issued.
+    // R <= 16: wave 0 loads and sums V in the register layout of the one-wave
+    // Gauss-Jordan inverse (below) and inverts it while the other waves load
+    // and sum the product partials; larger R: Gram element tid is loaded here
+    // and summed after the product loads have been issued.
     const bool wave_inv = R <= 16;
     __shared__ int s_failed;
     double vv[kMaxParts];
@@ -90,8 +90,41 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
         for (int c = 0; c < kMaxParts; ++c)
             vv[c] = (tid < R * R && c < a.vparts) ? a.vpart[(size_t)c * R * R + tid] : 0.0;
     }
+    // R <= 16: wave 0 sums the Gram partials into the register layout of the
+    // one-wave inverse, and the inverse runs while the other waves load the
+    // products.  Real factors: the product loads wait for the Gram sums (a
+    // barrier), so that the few Gram loads do not queue behind them (measured
+    // faster); the mixed path, with twice the product loads, starts them at
+    // once (measured faster there).
+    double vw[4] = {0.0, 0.0, 0.0, 0.0};
+    if (wave_inv) {
+        if (tid < kWave) {
+            const int j = tid & 15, i0 = tid >> 4;
+            double vq[4][kMaxParts];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + 4 * q;
+                const int e = (i < R && j < R) ? i * R + j : 0;
+#pragma unroll
+                for (int c = 0; c < kMaxParts; ++c) {
+                    const int cc = c < a.vparts ? c : 0;
+                    vq[q][c] = a.vpart[(size_t)cc * R * R + e];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + 4 * q;
+                double acc = 0.0;
+#pragma unroll
+                for (int c = 0; c < kMaxParts; ++c)
+                    if (c < a.vparts) acc += vq[q][c];
+                vw[q] = (i < R && j < R) ? acc : 0.0;
+            }
+        }
+        if (!a.mix) __syncthreads();  // uniform condition
+    }
     // The product partials: all threads, or (R <= 16) waves 1.. while wave 0
-    // loads and inverts V.
+    // inverts V.
     const int yt = wave_inv ? tid - kWave : tid, ys = wave_inv ? kStepThreads - kWave : kStepThreads;
     if (yt >= 0) {
         constexpr int VL = 16 / sizeof(T);  // values per 16-byte load
@@ -214,25 +247,7 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
     int failed;
     if (wave_inv) {
         if (tid < kWave) {  // the whole of wave 0
-            const int j = tid & 15, i0 = tid >> 4;
-            double v[4], vq[4][kMaxParts];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = i0 + 4 * q;
-                const bool in = i < R && j < R;
-                const int e = in ? i * R + j : 0;
-#pragma unroll
-                for (int c = 0; c < kMaxParts; ++c) {
-                    const int cc = c < a.vparts ? c : 0;
-                    vq[q][c] = a.vpart[(size_t)cc * R * R + e];
-                }
-                double acc = 0.0;
-#pragma unroll
-                for (int c = 0; c < kMaxParts; ++c)
-                    if (c < a.vparts) acc += vq[q][c];
-                v[q] = in ? acc : 0.0;
-            }
-            const int f = gj_wave_from_regs(v, B1, B3, R, ld);
+            const int f = gj_wave_from_regs(vw, B1, B3, R, ld);
             if (tid == 0) s_failed = f;
         }
         __syncthreads();
