@@ -7,7 +7,7 @@ library never does, and this package imports nothing from it.
 Plain, slow and written for checking by eye against Battaglino, Ballard and
 Kolda, "A Practical Randomized CP Tensor Decomposition": every function cites
 the section, equation or algorithm it follows.  numpy/scipy supply the
-library steps (QR least squares, FFT, SVD, matrix products).
+library steps (SVD-based least squares, FFT, SVD, matrix products).
 
 Modules:
   philox    Philox4x64-10 and the method's random draws (samples, signs, fit set)

@@ -1,7 +1,8 @@
 """FP64 reference of CPRAND (Alg. 3) and CPRAND-MIX (Alg. 4), step by step.
 
 Test infrastructure (see oracle/__init__.py).  Every function takes the
-paper's steps in the paper's order; numpy's QR-based least squares, FFT and
+paper's steps in the paper's order; numpy's least squares (LAPACK gelsd, SVD
+based; the same minimiser as the paper's QR for full-rank Z_S), FFT and
 matrix products serve as library steps.
 
 Conventions: X is a numpy array of shape dims (FP64, or complex128 once
@@ -66,8 +67,9 @@ def sampled_normal_blocks(X, idx, A, n, w=None):
 
 
 def sampled_ls(X, idx, A, n, w=None):
-    """A^(n) = argmin_A || Z_S A^T - X_S^T ||_F (Alg. 3), solved by QR-based
-    least squares.  Importance weights scale the rows by sqrt(w)."""
+    """A^(n) = argmin_A || Z_S A^T - X_S^T ||_F (Alg. 3), solved by LAPACK's
+    SVD-based least squares (the paper uses QR; both give the minimiser when
+    Z_S has full column rank).  Importance weights scale the rows by sqrt(w)."""
     Z = skr(idx, A, n)
     Xs = sample_fibers(X, idx, n)
     if w is not None:
