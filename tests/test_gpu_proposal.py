@@ -10,7 +10,7 @@ from oracle import leverage as OL
 from oracle import mlp as OM
 from oracle import proposal as OP
 from oracle import score as OS
-from gpu_util import dev, factors_dev, rel, view_of
+from gpu_util import close, dev, factors_dev, rel, view_of
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +37,7 @@ def test_marginal_proposal_matches_exact_leverage(dims, R, n):
     L = OL.krp_marginals([A[m] for m in others])
     for k, m in enumerate(others):
         want = (1 - alpha) * L[k] / L[k].sum() + alpha / dims[m]
-        assert rel(_probs(cdf[m]), want) < 2e-4, (m, rel(_probs(cdf[m]), want))
+        close(_probs(cdf[m]), want, 2e-4)
 
 
 def test_learned_proposal_matches_oracle_network():
@@ -49,7 +49,7 @@ def test_learned_proposal_matches_oracle_network():
     for m in (0, 2):
         others = [A[k] for k in range(3) if k not in (n, m)]
         want = OM.proposal_probs(theta.astype(np.float32).astype(np.float64), A[m], others, 0.2)
-        assert rel(_probs(cdf[m]), want) < 1e-4
+        close(_probs(cdf[m]), want, 1e-4)
 
 
 def test_features_and_targets_match_oracle():
@@ -64,7 +64,7 @@ def test_features_and_targets_match_oracle():
         Xr = OM.row_features(A[m], others)
         tr = OM.targets([A[k] for k in K], K.index(m))
         assert np.allclose(X[off:off + dims[m]], Xr, atol=2e-4, rtol=1e-4)
-        assert rel(t[off:off + dims[m]], tr) < 1e-5
+        close(t[off:off + dims[m]], tr, 1e-5)
         off += dims[m]
 
 
@@ -80,12 +80,12 @@ def test_network_forward_gradient_and_adam_match_oracle():
     pd = dev(theta)
     z = P.cprand_mlp_forward(pd, dev(X))
     zr, _ = OM.forward(th64, X.astype(np.float64))
-    assert rel(z.cpu().numpy(), zr) < 1e-5
+    close(z.cpu().numpy(), zr, 1e-5)
     goff = dev(np.array(bounds, dtype=np.int64))
     g, loss = P.cprand_mlp_grad(pd, dev(X), dev(t), goff)
     lr_, gr = OM.grad_fn(th64, X.astype(np.float64), t.astype(np.float64), groups)
     assert abs(loss.item() - lr_) < 1e-5 * max(1.0, abs(lr_))
-    assert rel(g.cpu().numpy(), gr) < 1e-4
+    close(g.cpu().numpy(), gr, 1e-4)
     m = torch.zeros_like(pd)
     v = torch.zeros_like(pd)
     P.cprand_mlp_adam(pd, g, m, v, 1, 1e-3)
