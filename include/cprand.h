@@ -130,23 +130,30 @@ int cprand_mttkrp_sampled(const cprand_tensor *X, int32_t n, const void *const *
 /* ---------------------------------------------------------------------------
  * Least-squares solve and normalisation (Alg. 3 solve and normalise steps).
  *
- * A = W V^{-1} by an FP64 Cholesky factorisation of V; if V is not
- * numerically positive definite, by its pseudo-inverse (cyclic Jacobi
- * eigen-decomposition, eigenvalues below 1e-12 of the largest dropped) and
- * *info = CPRAND_W_PINV.  With W_refine != NULL (float, I_n x R, the MTTKRP
- * of the same samples from FP32 data) one refinement step follows:
- * A += (W_refine - A V) V^{-1}.  The columns of A are then scaled to unit
- * 2-norm and lambda_out receives the norms (a zero column stays zero with
- * lambda 0).
+ * A = W V^{-1} through the normal equations, in FP64: V is inverted by
+ * Gauss-Jordan elimination without pivoting (V is symmetric positive
+ * definite when Z_S has full column rank; its pivots are then the squared
+ * diagonal of its Cholesky factor).  If a pivot falls below 1e-12 of the
+ * largest diagonal entry, V is diagonalised by cyclic Jacobi rotations and
+ * its pseudo-inverse (eigenvalues below 1e-12 of the largest dropped) is
+ * used instead, which gives the minimum-norm solution, and *info =
+ * CPRAND_W_PINV.  With W_refine and V_refine (the MTTKRP, float, I_n x R
+ * row-major, and the Gram, FP64 R x R, of the same samples from FP32 data
+ * and FP32 Khatri-Rao rows) one step of iterative refinement follows: the
+ * residual of the FP32 normal equations is corrected with the inverse of V,
+ * A += (W_refine - A V_refine) V^{-1}.  The columns of A are then scaled to
+ * unit 2-norm and lambda_out receives the norms (a zero column stays zero
+ * with lambda 0).
  *
  *   V        device R x R FP64          dtype   CPRAND_F64 or CPRAND_F32, the
  *   W        device I_n x R row-major            type of W and A_out
  *   A_out    device I_n x R row-major   info    device int32 or NULL
- *   lambda_out device R doubles
+ *   lambda_out device R doubles         W_refine, V_refine  device, both or neither
+ *   workspace  ceil(I_n / 32) * R * 8 bytes
  */
 int cprand_solve(int32_t I_n, int32_t R, const double *V, const void *W, int32_t dtype,
-                 const float *W_refine, void *A_out, double *lambda_out, int32_t *info,
-                 void *workspace, size_t workspace_bytes, void *stream);
+                 const float *W_refine, const double *V_refine, void *A_out, double *lambda_out,
+                 int32_t *info, void *workspace, size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Sampled fit estimate (Section 3.4).
@@ -264,7 +271,8 @@ int cprand_mlp_train(float *params, const float *X, const float *t, const int64_
 #define CPRAND_MIX_FFT 1
 
 #define CPRAND_PREC_NATIVE 0       /* arithmetic in the tensor's own type (F64 or F32) */
-#define CPRAND_PREC_BF16_REFINE 1  /* BF16 products, FP32 refinement, FP64 solve */
+#define CPRAND_PREC_BF16_REFINE 1  /* BF16 products, FP64 solve, FP32 refinement (see refine_every) */
+#define CPRAND_PREC_BF16 2         /* BF16 products, FP64 solve, no refinement */
 
 #define CPRAND_PROPOSAL_UNIFORM 0
 #define CPRAND_PROPOSAL_TABLE 1    /* caller-provided integer proposals, fixed */
@@ -291,6 +299,9 @@ typedef struct cprand_opts {
     double alpha;         /* uniform share of importance proposals */
     const uint64_t *const *proposal_cdf; /* PROPOSAL_TABLE: host array of `order` device CDFs */
     const float *mlp_params;            /* PROPOSAL_LEARNED: device, cprand_mlp_param_count() floats */
+    int32_t refine_every; /* PREC_BF16_REFINE: 1 = refine every solve; 0 = BF16 solves until the stop
+                             rule first holds (or one iteration before max_iters), then refined
+                             solves until it holds again */
 } cprand_opts;
 
 typedef struct cprand_report {
@@ -306,6 +317,7 @@ typedef struct cprand_report {
     double layout_ms[CPRAND_MAX_ORDER];  /* mode-major copy for each mode, 0 when none or fused */
     int32_t fused;          /* setup work folded into the mixing passes: bit 0, ||X|| in the first
                                pass; bit 1, the last mode's mode-major copy written by the last pass */
+    int32_t refined_from;   /* first iteration (0-based) with refined solves, -1 if none */
 } cprand_report;
 
 typedef struct cprand_plan cprand_plan;

@@ -127,7 +127,7 @@ def cprand_mttkrp_sampled(X, n, A, R, S, idx, w=None, unmix_signs=None, W=None, 
     return W, V
 
 
-def cprand_solve(V, W, W_refine=None, A_out=None, lambda_out=None, info=None, ws=None):
+def cprand_solve(V, W, W_refine=None, V_refine=None, A_out=None, lambda_out=None, info=None, ws=None):
     In, R = W.shape
     dtype = F64 if W.dtype == torch.float64 else F32
     if A_out is None:
@@ -138,8 +138,8 @@ def cprand_solve(V, W, W_refine=None, A_out=None, lambda_out=None, info=None, ws
         info = torch.zeros(1, dtype=torch.int32, device=W.device)
     if ws is None:
         ws = torch.empty(max(256, math.ceil(In / 32) * R * 8), dtype=torch.uint8, device=W.device)
-    _check(_lib.cprand_solve(In, R, _ptr(V), _ptr(W), dtype, _ptr(W_refine), _ptr(A_out), _ptr(lambda_out),
-                             _ptr(info), _ptr(ws), ws.numel(), _stream()))
+    _check(_lib.cprand_solve(In, R, _ptr(V), _ptr(W), dtype, _ptr(W_refine), _ptr(V_refine), _ptr(A_out),
+                             _ptr(lambda_out), _ptr(info), _ptr(ws), ws.numel(), _stream()))
     return A_out, lambda_out, info
 
 
@@ -289,13 +289,14 @@ def cprand_mlp_train(params, X, t, group_off, epochs, lr=1e-3):
 
 def make_opts(R, S, P_hat=2 ** 14, max_iters=50, seed=0, tol=0.0, fit_target=2.0, patience=0,
               mix=MIX_NONE, precision=PREC_NATIVE, proposal=PROPOSAL_UNIFORM, layout=0, use_graph=1,
-              alpha=0.1, proposal_cdf=None, mlp_params=None):
+              alpha=0.1, proposal_cdf=None, mlp_params=None, refine_every=0):
     o = _abi.cprand_opts()
     o.R, o.S, o.P_hat, o.max_iters = R, S, P_hat, max_iters
     o.seed = seed
     o.tol, o.fit_target, o.patience = tol, (2.0 if fit_target is None else fit_target), patience
     o.mix, o.precision, o.proposal, o.layout, o.use_graph = mix, precision, proposal, layout, use_graph
     o.alpha = alpha
+    o.refine_every = refine_every
     keep = []
     if proposal_cdf is not None:
         arr = (C.c_void_p * len(proposal_cdf))(*[c.data_ptr() for c in proposal_cdf])
@@ -332,6 +333,7 @@ class Plan:
                 "setup_ms": rep.setup_ms, "loop_ms": rep.loop_ms, "norm_ms": rep.norm_ms,
                 "mix_ms": [rep.mix_ms[i] for i in range(order)],
                 "layout_ms": [rep.layout_ms[i] for i in range(order)], "fused": rep.fused,
+                "refined_from": rep.refined_from,
                 "fit_history": [hist[i] for i in range(rep.iters)],
                 "proposal_history": [props[i] for i in range(rep.iters)]}
 

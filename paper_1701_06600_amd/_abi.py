@@ -34,7 +34,7 @@ class cprand_opts(C.Structure):
                 ("patience", C.c_int32), ("mix", C.c_int32), ("precision", C.c_int32),
                 ("proposal", C.c_int32), ("layout", C.c_int32), ("use_graph", C.c_int32),
                 ("alpha", C.c_double), ("proposal_cdf", C.POINTER(C.c_void_p)),
-                ("mlp_params", C.c_void_p)]
+                ("mlp_params", C.c_void_p), ("refine_every", C.c_int32)]
 
 
 class cprand_report(C.Structure):
@@ -43,7 +43,8 @@ class cprand_report(C.Structure):
                 ("fit_history", C.POINTER(C.c_double)),
                 ("proposal_history", C.POINTER(C.c_int32)),
                 ("norm_ms", C.c_double), ("mix_ms", C.c_double * MAX_ORDER),
-                ("layout_ms", C.c_double * MAX_ORDER), ("fused", C.c_int32)]
+                ("layout_ms", C.c_double * MAX_ORDER), ("fused", C.c_int32),
+                ("refined_from", C.c_int32)]
 
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcprand.so")
@@ -60,7 +61,8 @@ SIGNATURES = [
                                         C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("cprand_solve", C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                               C.c_void_p]),
     ("cprand_fit_est", C.c_int, [C.POINTER(cprand_tensor), C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p,
                                  C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p, C.c_size_t,
                                  C.c_void_p]),

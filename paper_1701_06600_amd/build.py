@@ -23,8 +23,13 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Wno-unused-result"]
 
 
-def _compile(src):
+def _compile(src, incremental=False):
     out = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if incremental and os.path.exists(out):
+        deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")]
+        deps.append(os.path.join(os.path.dirname(HERE), "include", "cprand.h"))
+        if max(os.path.getmtime(d) for d in deps) < os.path.getmtime(out):
+            return out
     cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -32,11 +37,14 @@ def _compile(src):
     return out
 
 
-def build(verbose=False, jobs=None):
+def build(verbose=False, jobs=None, incremental=False):
+    """incremental=True skips sources whose object is newer than the source,
+    every header and include/cprand.h (a developer shortcut; the default
+    recompiles everything)."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(8, len(SOURCES), os.cpu_count() or 1)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-Wl,-z,defs", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,5 +57,5 @@ def build(verbose=False, jobs=None):
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -67,6 +67,9 @@ struct cprand_plan {
     int xkind = 0;
     int64_t P = 1;
     bool dbl = false, mix = false, bf16 = false, refine = false;
+    // BF16 form with refinement: whether the current iterations refine (all
+    // of them with refine_every; else from the first stop-rule hit on)
+    bool ref_now = true;
     int gkind = 0;
     View gview[CPRAND_MAX_ORDER], rview[CPRAND_MAX_ORDER];
     void *xhat = nullptr;
@@ -151,7 +154,7 @@ int vec_elems(int kind) { return (int)(16 / elem_size(kind)); }
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
-// host stopping rule, identical in meaning to the reference: stop after
+// host stopping rule (Section 3.4 and the rules of Section 4.2): stop after
 // iteration t (0-based) when t+1 >= max_iters, |F_t - F_{t-1}| <= tol,
 // F_t >= fit_target, or the best F has not improved for `patience` steps.
 struct Stop {
@@ -252,22 +255,24 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
     hipError_t e = hipSuccess;
     const int N = p->N, R = p->o.R;
     const int sb = ic ? (int)(ic->t & 1) : 0;
+    // the FP32 refinement gather and step run only in the refined phase
+    const bool refine = p->refine && p->ref_now;
     for (int n = 0; n < N && e == hipSuccess; ++n) {
         const View &v = p->gview[n];
         const void *vd = view_ptr(p, v, xdata);
         const int64_t In = p->dims[n];
         // the whole post-gather step in one workgroup when it fits in LDS
         bool fused = step_finish_lds((int32_t)In, R, p->mix) <= 156 * 1024;
-        const bool rcontig = p->refine && (p->rview[n].data ? true : contig_x[n]);
+        const bool rcontig = refine && (p->rview[n].data ? true : contig_x[n]);
         GatherPlan gp = plan_gather(p->gkind, R, p->o.S, In, v.data ? v.contig : contig_x[n],
                                     fused ? kChunksFused : kChunksSplit);
-        GatherPlan gr = p->refine ? plan_gather(K_F32, R, p->o.S, In, rcontig, fused ? kChunksFused : kChunksSplit)
+        GatherPlan gr = refine ? plan_gather(K_F32, R, p->o.S, In, rcontig, fused ? kChunksFused : kChunksSplit)
                                   : GatherPlan{};
-        if (fused && (gp.chunks > kChunksFused || (p->refine && gr.chunks > kChunksFused))) {
+        if (fused && (gp.chunks > kChunksFused || (refine && gr.chunks > kChunksFused))) {
             // the LDS limit shrank the chunks: too many partials for the fused step
             fused = false;
             gp = plan_gather(p->gkind, R, p->o.S, In, v.data ? v.contig : contig_x[n], kChunksSplit);
-            if (p->refine) gr = plan_gather(K_F32, R, p->o.S, In, rcontig, kChunksSplit);
+            if (refine) gr = plan_gather(K_F32, R, p->o.S, In, rcontig, kChunksSplit);
         }
         GatherArgs ga{};
         ga.mi.order = N;
@@ -319,7 +324,7 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         }
         ga.wpart = p->wpart;
         ga.vpart = p->vpart;
-        if (p->refine) {
+        if (refine) {
             // the FP32 refinement gather (same samples, its own partials) on a
             // second stream, forked before and joined after the BF16 gather
             const View &rv = p->rview[n];
@@ -334,7 +339,7 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
             if (e == hipSuccess) e = hipEventRecord(p->ev_ref[1], p->rst);
         }
         if (e == hipSuccess) e = launch_gather(gp, ga, st);
-        if (e == hipSuccess && p->refine) e = hipStreamWaitEvent(st, p->ev_ref[1], 0);
+        if (e == hipSuccess && refine) e = hipStreamWaitEvent(st, p->ev_ref[1], 0);
         if (e != hipSuccess) break;
         if (fused) {
             StepArgs sa{};
@@ -350,12 +355,14 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
             sa.wdouble = p->dbl;
             sa.mix = p->mix;
             sa.sign = p->mix ? p->signs + p->seg_off[n] : nullptr;
-            if (p->refine) {
+            if (refine) {
                 sa.Wref = (const float *)p->rpart;
                 sa.wrefparts = gr.chunks;
                 sa.rps = (int64_t)R * In;
                 sa.rsi = 1;
                 sa.rsr = In;
+                sa.vref = p->vrpart;
+                sa.vrefparts = gr.chunks;
             }
             sa.A = p->fac[n];
             sa.Ahat = p->mix ? p->fhat[n] : nullptr;
@@ -404,12 +411,14 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         }
         sa.wsi = 1;
         sa.wsr = In;
-        if (p->refine) {
+        if (refine) {
             sa.Wref = (const float *)p->rpart;
             sa.wrefparts = gr.chunks;
             sa.rps = (int64_t)R * In;
             sa.rsi = 1;
             sa.rsr = In;
+            sa.vref = p->vrpart;
+            sa.vrefparts = gr.chunks;
         }
         sa.A = p->fac[n];
         sa.adouble = p->dbl;
@@ -823,22 +832,44 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
     if (e == hipSuccess) e = hipEventRecord(p->ev[1], st);
     if (e != hipSuccess) return hip_fail(e, "setup");
 
-    // the ALS loop
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-    if (p->o.use_graph) {
-        e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed);
-        if (e == hipSuccess) {
-            hipError_t e2 = enqueue_iteration(p, X->data, contig_x, p->cap);
-            e = hipStreamEndCapture(p->cap, &graph);
-            if (e2 != hipSuccess) e = e2;
+    // The BF16 form with refinement follows a schedule unless refine_every
+    // is set: BF16 solves only, until the stop rule first holds (or one
+    // iteration before the cap), then refined solves until it holds again,
+    // so at least the last iteration is refined.
+    const bool sched = p->refine && !p->o.refine_every && p->o.max_iters > 1;
+    p->ref_now = !sched;
+    int refined_from = p->refine ? (sched ? -1 : 0) : -1;
+
+    // the ALS loop: one graph per iteration kind (BF16-only and refined)
+    hipGraphExec_t execs[2] = {nullptr, nullptr};
+    hipGraph_t graphs[2] = {nullptr, nullptr};
+    auto destroy_graphs = [&]() {
+        for (int k = 0; k < 2; ++k) {
+            if (execs[k]) (void)hipGraphExecDestroy(execs[k]);
+            if (graphs[k]) (void)hipGraphDestroy(graphs[k]);
+            execs[k] = nullptr;
+            graphs[k] = nullptr;
         }
-        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    };
+    if (p->o.use_graph) {
+        for (int k = sched ? 0 : 1; k < 2 && e == hipSuccess; ++k) {
+            p->ref_now = k == 1;
+            e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed);
+            if (e == hipSuccess) {
+                hipError_t e2 = enqueue_iteration(p, X->data, contig_x, p->cap);
+                e = hipStreamEndCapture(p->cap, &graphs[k]);
+                if (e2 != hipSuccess) e = e2;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&execs[k], graphs[k], nullptr, nullptr, 0);
+        }
+        p->ref_now = !sched;
         if (e != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
+            destroy_graphs();
             return hip_fail(e, "graph capture");
         }
     }
+    auto cur_exec = [&]() { return execs[p->ref_now ? 1 : 0]; };
+    const bool graphed = p->o.use_graph != 0;
     Stop stop(p->o);
     int it = 0;
     double F = 0.0;
@@ -882,7 +913,7 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
         return launch_fill_u64((uint64_t *)p->alpha_dev, bits, st);
     };
     auto run_iteration = [&]() {
-        hipError_t r = exec ? hipGraphLaunch(exec, st) : enqueue_iteration(p, X->data, contig_x, st);
+        hipError_t r = graphed ? hipGraphLaunch(cur_exec(), st) : enqueue_iteration(p, X->data, contig_x, st);
         if (r == hipSuccess) r = hipEventRecord(p->ev[2], st);
         if (r == hipSuccess) r = hipEventSynchronize(p->ev[2]);
         return r;
@@ -900,14 +931,27 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
         // waited for the fit of t.
         auto launch_one = [&](int t) {
             hipError_t r;
-            if (exec) {
-                r = hipGraphLaunch(exec, st);
+            if (graphed) {
+                r = hipGraphLaunch(cur_exec(), st);
                 if (r == hipSuccess) r = hipEventRecord(p->ev[t & 1 ? 3 : 2], st);
             } else {
                 const IterCtl ic{(uint64_t)t, p->fst, p->ev_state[t & 1]};
                 r = enqueue_iteration(p, X->data, contig_x, st, &ic);
                 if (r == hipSuccess) r = hipEventRecord(p->ev[t & 1 ? 3 : 2], p->fst);
             }
+            return r;
+        };
+        // the state after iteration t back into the live factors and lambda
+        auto restore = [&](int t) {
+            const char *sb = (const char *)p->snapbuf[t & 1];
+            size_t off = 0;
+            hipError_t r = hipSuccess;
+            for (int m = 0; m < N && r == hipSuccess; ++m) {
+                const size_t b = (size_t)p->dims[m] * R * tsz * (p->mix ? 2 : 1);
+                r = hipMemcpyAsync(p->mix ? p->fhat[m] : p->fac[m], sb + off, b, hipMemcpyDeviceToDevice, st);
+                off += b;
+            }
+            if (r == hipSuccess) r = hipMemcpyAsync(p->lambda, sb + off, (size_t)R * 8, hipMemcpyDeviceToDevice, st);
             return r;
         };
         bool ahead = false;
@@ -923,7 +967,22 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
                 break;
             }
             levels.push_back(0);
-            if (stop(it, F)) {
+            const bool s = stop(it, F);
+            if (sched && !p->ref_now && (s || it + 2 >= p->o.max_iters)) {
+                // switch to refined solves from iteration it + 1: drop the
+                // BF16 iteration already launched and restart it refined
+                e = hipStreamSynchronize(st);
+                if (e == hipSuccess) e = hipStreamSynchronize(p->fst);
+                if (e == hipSuccess && ahead) e = restore(it);
+                // graphs read the iteration number from the device counter
+                // that the dropped iteration has already advanced
+                if (e == hipSuccess && graphed) e = launch_fill_u64(p->t_dev, (uint64_t)(it + 1), st);
+                p->ref_now = true;
+                refined_from = it + 1;
+                if (e == hipSuccess) e = launch_one(it + 1);
+                continue;
+            }
+            if (s) {
                 ++it;
                 break;
             }
@@ -931,17 +990,7 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
         }
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e == hipSuccess) e = hipStreamSynchronize(p->fst);
-        if (e == hipSuccess && ahead) {  // undo the iteration launched past the stop
-            const char *sb = (const char *)p->snapbuf[(it - 1) & 1];
-            const size_t tsz = p->dbl ? 8 : 4;
-            size_t off = 0;
-            for (int m = 0; m < N && e == hipSuccess; ++m) {
-                const size_t b = (size_t)p->dims[m] * R * tsz * (p->mix ? 2 : 1);
-                e = hipMemcpyAsync(p->mix ? p->fhat[m] : p->fac[m], sb + off, b, hipMemcpyDeviceToDevice, st);
-                off += b;
-            }
-            if (e == hipSuccess) e = hipMemcpyAsync(p->lambda, sb + off, (size_t)R * 8, hipMemcpyDeviceToDevice, st);
-        }
+        if (e == hipSuccess && ahead) e = restore(it - 1);  // undo the iteration launched past the stop
     }
     for (; p->adaptive && it < p->o.max_iters; ++it) {
         const bool duel = p->adaptive && level < 2 && it > 0 && ((it + 1) & it) == 0;
@@ -992,13 +1041,18 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
             }
         }
         if (e != hipSuccess) break;
-        if (stop(it, F)) {
+        const bool s = stop(it, F);
+        if (sched && !p->ref_now && (s || it + 2 >= p->o.max_iters)) {
+            p->ref_now = true;  // refined solves from the next iteration on
+            refined_from = it + 1;
+            continue;
+        }
+        if (s) {
             ++it;
             break;
         }
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    destroy_graphs();
     if (e != hipSuccess && isfinite(F)) return hip_fail(e, "ALS loop");
     if (!isfinite(F)) return set_error(CPRAND_ENAN, "non-finite fit estimate at iteration %d", it);
     // under mixing the loop keeps only A-hat: A = D_n F_n^* A-hat (Alg. 4, final unmix)
@@ -1031,6 +1085,7 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
         (void)hipEventElapsedTime(&ms, tev[0], tev[1]);
         rep->norm_ms = ms;
         rep->fused = (p->mix && norm_done ? 1 : 0) | (copied_last ? 2 : 0);
+        rep->refined_from = refined_from < it ? refined_from : -1;
         for (int m = 0; m < CPRAND_MAX_ORDER; ++m) {
             rep->mix_ms[m] = 0.0;
             rep->layout_ms[m] = 0.0;

@@ -130,6 +130,71 @@ WsLayout ws_layout(const cprand_tensor *X, int32_t R, int32_t S, int32_t P_hat) 
     return w;
 }
 
+int check_mttkrp_args(const cprand_tensor *X, int32_t n, const void *const *A, int32_t R, int32_t S,
+                      const int32_t *idx, const double *w, const int8_t *unmix_signs, const void *W, const double *V) {
+    int rc = check_tensor(X, "X");
+    if (rc) return rc;
+    if (n < 0 || n >= X->order) return set_error(CPRAND_EINVAL, "mode %d outside [0, %d)", n, X->order);
+    if (R < 1 || R > CPRAND_MAX_RANK) return set_error(CPRAND_EINVAL, "R = %d outside [1, %d]", R, CPRAND_MAX_RANK);
+    if (S < 1) return set_error(CPRAND_EINVAL, "S = %d < 1", S);
+    if (!A) return set_error(CPRAND_EINVAL, "A is NULL");
+    for (int m = 0; m < X->order; ++m)
+        if (m != n && !A[m]) return set_error(CPRAND_EINVAL, "A[%d] is NULL", m);
+    if (!idx || !W || !V) return set_error(CPRAND_EINVAL, "idx, W and V must be non-NULL");
+    const int kind = kind_of(X->dtype);
+    const bool cplx = kind == K_C64 || kind == K_C128;
+    if (cplx && !unmix_signs) return set_error(CPRAND_EINVAL, "a mixed tensor needs unmix_signs");
+    if (cplx && w) return set_error(CPRAND_EUNSUPPORTED, "importance weights with a mixed tensor");
+    return CPRAND_OK;
+}
+
+void mttkrp_scratch_bytes(const cprand_tensor *X, int32_t n, int32_t R, int32_t S, size_t *wpart, size_t *vpart) {
+    const int kind = kind_of(X->dtype);
+    const bool contig = fibers_vectorizable(X->data, kind, X->strides, X->order, n);
+    GatherPlan gp = plan_gather(kind, R, S, X->dims[n], contig);
+    const size_t tsz = (kind == K_F64 || kind == K_C128) ? 8 : 4;
+    *wpart = gp.wpart_elems() * tsz;
+    *vpart = gp.vpart_elems() * 8;
+}
+
+int mttkrp_sampled_run(const cprand_tensor *X, int32_t n, const void *const *A, int32_t R, int32_t S,
+                       const int32_t *idx, const double *w, const int8_t *unmix_signs, void *W, double *V,
+                       void *wpart, double *vpart, void *wtmp, hipStream_t st) {
+    const int kind = kind_of(X->dtype);
+    const bool cplx = kind == K_C64 || kind == K_C128;
+    const bool contig = fibers_vectorizable(X->data, kind, X->strides, X->order, n);
+    GatherPlan gp = plan_gather(kind, R, S, X->dims[n], contig);
+    GatherArgs ga{};
+    ga.mi = mode_info(X, n);
+    ga.X = X->data;
+    for (int m = 0; m < X->order; ++m) ga.A.p[m] = (m == n) ? nullptr : A[m];
+    ga.idx = idx;
+    ga.w = w;
+    ga.wpart = wpart;
+    ga.vpart = vpart;
+    hipError_t e = launch_gather(gp, ga, st);
+    if (e != hipSuccess) return hip_fail(e, "gather kernel");
+    if (!cplx) {
+        e = launch_reduce_wv(gp, ga.wpart, ga.vpart, W, V, st);
+    } else {
+        const bool dbl = kind == K_C128;
+        FftPlan *fp = fft_plan_get(X->dims[n], dbl, &e);
+        if (!fp) return set_error(CPRAND_EUNSUPPORTED, "mode length %lld does not factor into 2,3,5,7",
+                                  (long long)X->dims[n]);
+        const void *y = ga.wpart;
+        int32_t np = gp.chunks;
+        if (np > 8) {  // many partials: sum them in parallel before the per-column transforms
+            e = launch_sum_parts(ga.wpart, np, (int64_t)2 * R * X->dims[n], dbl, wtmp, st);
+            if (e != hipSuccess) return hip_fail(e, "partial sums");
+            y = wtmp;
+            np = 1;
+        }
+        e = launch_unmix(fp, dbl, (int32_t)X->dims[n], R, np, y, unmix_signs, W, true, st);
+        if (e == hipSuccess) e = launch_reduce_wv(gp, nullptr, ga.vpart, nullptr, V, st);
+    }
+    return e == hipSuccess ? CPRAND_OK : hip_fail(e, "mttkrp reduction");
+}
+
 }  // namespace cprand
 
 using namespace cprand;
@@ -193,65 +258,26 @@ int cprand_mttkrp_sampled(const cprand_tensor *X, int32_t n, const void *const *
                           const int32_t *idx, const double *w, const int8_t *unmix_signs, void *W, double *V,
                           void *workspace, size_t workspace_bytes, void *stream) {
     g_last_error.clear();
-    int rc = check_tensor(X, "X");
+    int rc = check_mttkrp_args(X, n, A, R, S, idx, w, unmix_signs, W, V);
     if (rc) return rc;
-    if (n < 0 || n >= X->order) return set_error(CPRAND_EINVAL, "mode %d outside [0, %d)", n, X->order);
-    if (R < 1 || R > CPRAND_MAX_RANK) return set_error(CPRAND_EINVAL, "R = %d outside [1, %d]", R, CPRAND_MAX_RANK);
-    if (S < 1) return set_error(CPRAND_EINVAL, "S = %d < 1", S);
-    if (!A) return set_error(CPRAND_EINVAL, "A is NULL");
-    for (int m = 0; m < X->order; ++m)
-        if (m != n && !A[m]) return set_error(CPRAND_EINVAL, "A[%d] is NULL", m);
-    if (!idx || !W || !V) return set_error(CPRAND_EINVAL, "idx, W and V must be non-NULL");
-    const int kind = kind_of(X->dtype);
-    const bool cplx = kind == K_C64 || kind == K_C128;
-    if (cplx && !unmix_signs) return set_error(CPRAND_EINVAL, "a mixed tensor needs unmix_signs");
-    if (cplx && w) return set_error(CPRAND_EUNSUPPORTED, "importance weights with a mixed tensor");
     const WsLayout L = ws_layout(X, R, S, 0);
     if (!workspace || workspace_bytes < L.total)
         return set_error(CPRAND_EINVAL, "workspace of %zu bytes needed", L.total);
-    hipStream_t st = (hipStream_t)stream;
-    const bool contig = fibers_vectorizable(X->data, kind, X->strides, X->order, n);
-    GatherPlan gp = plan_gather(kind, R, S, X->dims[n], contig);
-    GatherArgs ga{};
-    ga.mi = mode_info(X, n);
-    ga.X = X->data;
-    for (int m = 0; m < X->order; ++m) ga.A.p[m] = (m == n) ? nullptr : A[m];
-    ga.idx = idx;
-    ga.w = w;
-    ga.wpart = (char *)workspace + L.wpart;
-    ga.vpart = (double *)((char *)workspace + L.vpart);
-    hipError_t e = launch_gather(gp, ga, st);
-    if (e != hipSuccess) return hip_fail(e, "gather kernel");
-    if (!cplx) {
-        e = launch_reduce_wv(gp, ga.wpart, ga.vpart, W, V, st);
-    } else {
-        const bool dbl = kind == K_C128;
-        FftPlan *fp = fft_plan_get(X->dims[n], dbl, &e);
-        if (!fp) return set_error(CPRAND_EUNSUPPORTED, "mode length %lld does not factor into 2,3,5,7",
-                                  (long long)X->dims[n]);
-        const void *y = ga.wpart;
-        int32_t np = gp.chunks;
-        if (np > 8) {  // many partials: sum them in parallel before the per-column transforms
-            void *ysum = (char *)workspace + L.wtmp;
-            e = launch_sum_parts(ga.wpart, np, (int64_t)2 * R * X->dims[n], dbl, ysum, st);
-            if (e != hipSuccess) return hip_fail(e, "partial sums");
-            y = ysum;
-            np = 1;
-        }
-        e = launch_unmix(fp, dbl, (int32_t)X->dims[n], R, np, y, unmix_signs, W, true, st);
-        if (e == hipSuccess) e = launch_reduce_wv(gp, nullptr, ga.vpart, nullptr, V, st);
-    }
-    return e == hipSuccess ? CPRAND_OK : hip_fail(e, "mttkrp reduction");
+    return mttkrp_sampled_run(X, n, A, R, S, idx, w, unmix_signs, W, V, (char *)workspace + L.wpart,
+                              (double *)((char *)workspace + L.vpart), (char *)workspace + L.wtmp,
+                              (hipStream_t)stream);
 }
 
 int cprand_solve(int32_t I_n, int32_t R, const double *V, const void *W, int32_t dtype, const float *W_refine,
-                 void *A_out, double *lambda_out, int32_t *info, void *workspace, size_t workspace_bytes,
-                 void *stream) {
+                 const double *V_refine, void *A_out, double *lambda_out, int32_t *info, void *workspace,
+                 size_t workspace_bytes, void *stream) {
     g_last_error.clear();
     if (I_n < 1) return set_error(CPRAND_EINVAL, "I_n = %d < 1", I_n);
     if (R < 1 || R > CPRAND_MAX_RANK) return set_error(CPRAND_EINVAL, "R = %d outside [1, %d]", R, CPRAND_MAX_RANK);
     if (dtype != CPRAND_F64 && dtype != CPRAND_F32) return set_error(CPRAND_EINVAL, "dtype must be F64 or F32");
     if (!V || !W || !A_out || !lambda_out) return set_error(CPRAND_EINVAL, "V, W, A_out, lambda_out must be non-NULL");
+    if ((W_refine == nullptr) != (V_refine == nullptr))
+        return set_error(CPRAND_EINVAL, "W_refine and V_refine must both be given or both be NULL");
     const size_t need = (size_t)ceil_div(I_n, 32) * R * 8;
     if (!workspace || workspace_bytes < need) return set_error(CPRAND_EINVAL, "workspace of %zu bytes needed", need);
     hipStream_t st = (hipStream_t)stream;
@@ -271,6 +297,8 @@ int cprand_solve(int32_t I_n, int32_t R, const double *V, const void *W, int32_t
     a.rps = 0;
     a.rsi = R;
     a.rsr = 1;
+    a.vref = V_refine;
+    a.vrefparts = 1;
     a.A = A_out;
     a.adouble = dtype == CPRAND_F64;
     a.colsq_part = (double *)workspace;

@@ -117,6 +117,8 @@ struct SolveArgs {
     const float *Wref;     // refinement MTTKRP (p, i, r) at Wref[p*rps + i*rsi + r*rsr], or NULL
     int32_t wrefparts;
     int64_t rps, rsi, rsr;
+    const double *vref;    // with Wref: Gram of the FP32 rows, parts x R x R
+    int32_t vrefparts;
     void *A;               // row-major In x R, unnormalised on output of solve
     bool adouble;
     double *colsq_part;    // [blocks][R]
@@ -139,6 +141,8 @@ struct StepArgs {
     const float *Wref;      // refinement partials or NULL
     int32_t wrefparts;
     int64_t rps, rsi, rsr;
+    const double *vref;     // with Wref: Gram partials of the FP32 rows
+    int32_t vrefparts;
     void *A;                // row-major In x R, real type (not written under mixing)
     void *Ahat;             // MIX: row-major In x R complex
     double *lambda;

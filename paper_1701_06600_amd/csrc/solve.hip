@@ -5,9 +5,11 @@
 // Every workgroup sums the Gram partials and inverts V in LDS (solve_device.hpp);
 // the factorisation is repeated per workgroup (R <= 64) so that no extra
 // launch or grid synchronisation is needed.  The workgroup then solves its
-// block of rows, A_i = W_i V^{-1}, optionally refines once against an FP32
-// right-hand side (A += (W_ref - A V) V^{-1}), and writes per-block column
-// sums of squares for the normalisation kernel.
+// block of rows, A_i = W_i V^{-1}, optionally takes one step of iterative
+// refinement against the FP32 normal equations (A += (W_ref - A V_ref) V^{-1},
+// the residual formed with the FP32 blocks and corrected with the inverse
+// already computed), and writes per-block column sums of squares for the
+// normalisation kernel.
 #include "kernels.hpp"
 #include "solve_device.hpp"
 
@@ -65,6 +67,13 @@ __global__ __launch_bounds__(NT) void solve_kernel(SolveArgs a) {
     }
     __syncthreads();
     if (a.Wref) {
+        // B3 <- V_ref: the residual is that of the FP32 normal equations
+        for (int p = tid; p < R * R; p += NT) {
+            double acc = 0.0;
+            for (int c = 0; c < a.vrefparts; ++c) acc += a.vref[(size_t)c * R * R + p];
+            B3[(p / R) * ld + p % R] = acc;
+        }
+        __syncthreads();
         for (int e = tid; e < nr * R; e += NT) {
             const int ii = e / R, r = e - ii * R;
             double s = 0.0;

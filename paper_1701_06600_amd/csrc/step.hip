@@ -396,6 +396,14 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
     }
     __syncthreads();
     if (a.Wref) {
+        // B3 <- V_ref, the Gram of the FP32 rows: the residual is that of the
+        // FP32 normal equations, the correction uses the inverse above
+        for (int p = tid; p < R * R; p += kStepThreads) {
+            double acc = 0.0;
+            for (int c = 0; c < a.vrefparts; ++c) acc += a.vref[(size_t)c * R * R + p];
+            B3[(p / R) * ld + p % R] = acc;
+        }
+        __syncthreads();
         for (int e = tid; e < In * R; e += kStepThreads) {
             const int i = e / R, r = e - i * R;
             float v[kMaxParts];
@@ -456,6 +464,7 @@ size_t step_finish_lds(int32_t In, int32_t R, bool mix) {
 
 hipError_t launch_step_finish(const StepArgs &a, bool dbl, hipStream_t st) {
     if (a.vparts > kMaxParts || a.wparts > kMaxParts || (a.Wref && a.wrefparts > kMaxParts)) return hipErrorInvalidValue;
+    if (a.Wref && (!a.vref || a.vrefparts < 1)) return hipErrorInvalidValue;
     if (a.mix && !a.Ahat) return hipErrorInvalidValue;
     const size_t lds = step_finish_lds(a.In, a.R, a.mix);
     if (dbl)

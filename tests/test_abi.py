@@ -99,9 +99,9 @@ def test_workspace_size_monotone_and_zero_on_bad_args():
 def test_solve_fit_mix_layout_validation():
     L = P._lib
     p16 = C.c_void_p(16)
-    assert L.cprand_solve(0, 4, p16, p16, _abi.F64, None, p16, p16, None, p16, 1 << 20, None) == P.EINVAL
-    assert L.cprand_solve(10, 4, p16, p16, _abi.BF16, None, p16, p16, None, p16, 1 << 20, None) == P.EINVAL
-    assert L.cprand_solve(10, 4, p16, p16, _abi.F64, None, p16, p16, None, p16, 8, None) == P.EINVAL
+    assert L.cprand_solve(0, 4, p16, p16, _abi.F64, None, None, p16, p16, None, p16, 1 << 20, None) == P.EINVAL
+    assert L.cprand_solve(10, 4, p16, p16, _abi.BF16, None, None, p16, p16, None, p16, 1 << 20, None) == P.EINVAL
+    assert L.cprand_solve(10, 4, p16, p16, _abi.F64, None, None, p16, p16, None, p16, 8, None) == P.EINVAL
     X = _tensor()
     A = (C.c_void_p * 3)(16, 16, 16)
     assert L.cprand_fit_est(C.byref(X), p16, A, p16, 4, 0, 1, p16, p16, 1 << 20, None) == P.EINVAL
@@ -149,3 +149,27 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(n, "sizeof")] == C.sizeof(st), n
         for f in st._fields_:
             assert got[(n, f[0])] == getattr(st, f[0]).offset, (n, f[0])
+
+
+def _header_defines():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for name, val in re.findall(r"#define\s+CPRAND_([A-Z0-9_]+)\s+\(?(-?\d+)\)?", text):
+        out[name] = int(val)
+    return out
+
+
+def test_binding_constants_match_header_defines():
+    """Every constant the binding passes across the ABI is #defined in the
+    header with the same value."""
+    d = _header_defines()
+    names = ["MAX_ORDER", "MAX_RANK", "OK", "W_PINV", "W_MAXIT", "W_FALLBACK", "EINVAL", "ENAN", "EHIP",
+             "ENOMEM", "EUNSUPPORTED", "F64", "F32", "BF16", "C64", "C128", "MIX_NONE", "MIX_FFT",
+             "PREC_NATIVE", "PREC_BF16_REFINE", "PREC_BF16", "PROPOSAL_UNIFORM", "PROPOSAL_TABLE",
+             "PROPOSAL_LEARNED", "PROPOSAL_MARGINAL", "PROPOSAL_MIXTURE"]
+    for n in names:
+        assert n in d, "CPRAND_%s is not #defined in the header" % n
+        assert getattr(_abi, n) == d[n], (n, getattr(_abi, n), d[n])
+    # and nothing the header defines is missing from the binding
+    for n in d:
+        assert hasattr(_abi, n), "CPRAND_%s has no binding constant" % n

@@ -87,20 +87,29 @@ def test_cprand_mix_f64_tracks_oracle(use_graph):
         assert np.allclose(a, b, atol=1e-7)
 
 
-@pytest.mark.parametrize("layout", [0, 1])
-def test_cprand_bf16_refined_reaches_fp64_fit(layout):
+@pytest.mark.parametrize("layout,use_graph,every", [(0, 0, 0), (1, 1, 0), (0, 1, 1), (1, 0, 1)])
+def test_cprand_bf16_refined_reaches_fp64_fit(layout, use_graph, every):
     """layout 0: BF16 and FP32 mode-major copies; layout 1: strided gathers
-    from one BF16 conversion of X and from X itself."""
+    from one BF16 conversion of X and from X itself.  every = 0: BF16 solves
+    until the stop rule holds, then refined solves; every = 1: refinement in
+    every solve."""
     p = synth.make_problem((40, 36, 32, 28), 5, congruence=0.5, noise=0.01, seed=9)
     X = synth.dense_tensor(p).astype(np.float32).astype(np.float64)
     S = 200
-    out, A = _run_gpu(X, p.init, 5, S, 4, torch.float32, max_iters=60, precision=P.PREC_BF16_REFINE, layout=layout)
-    lam_r, A_r, _ = OC.cprand(X, 5, S, p.init, 4, 60)
+    out, A = _run_gpu(X, p.init, 5, S, 4, torch.float32, max_iters=60, tol=1e-4, precision=P.PREC_BF16_REFINE,
+                      layout=layout, use_graph=use_graph, refine_every=every)
+    lam_r, A_r, hist_r = OC.cprand(X, 5, S, p.init, 4, 60, tol=1e-4)
+    F_r = OC.exact_fit(X, lam_r, A_r)
     F = OC.exact_fit(X, out["lambda"].cpu().numpy(), A)
-    assert abs(F - OC.exact_fit(X, lam_r, A_r)) < 1e-3
+    assert abs(F - F_r) < 1e-3
+    if every:
+        assert out["refined_from"] == 0
+    else:
+        assert 0 < out["refined_from"] < out["iters"], (out["refined_from"], out["iters"])
     out2, A2 = _run_gpu(X, p.init, 5, S, 4, torch.float32, max_iters=60, precision=P.PREC_BF16, layout=layout)
     F2 = OC.exact_fit(X, out2["lambda"].cpu().numpy(), A2)
-    assert abs(F2 - OC.exact_fit(X, lam_r, A_r)) < 1e-3
+    assert abs(F2 - F_r) < 1e-3
+    assert out2["refined_from"] == -1
 
 
 @pytest.mark.parametrize("mix", [0, 1])

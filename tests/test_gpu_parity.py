@@ -160,6 +160,26 @@ def test_mttkrp_bf16_error_bound():
         close(V.cpu().numpy(), Vr, 1e-2, "BF16 V mode %d" % n)
 
 
+@pytest.mark.parametrize("dims,R,S", [((150, 40, 24, 9), 20, 1000), ((67, 33, 29), 7, 333)])
+def test_mttkrp_bf16_matches_bf16_oracle(dims, R, S):
+    """Against the oracle of the BF16 product (the same roundings, sums in
+    FP64): only the FP32 accumulation of the MFMA remains."""
+    from oracle import precision as OR
+    rng = _rng(17)
+    X = rng.standard_normal(dims).astype(np.float32)
+    A = [rng.standard_normal((I, R)).astype(np.float32) for I in dims]
+    Xv = view_of(X, torch.float32)
+    Ad = factors_dev(A, torch.float32)
+    for n in range(len(dims)):
+        Y = P.mode_major_copy(Xv, n, dtype=torch.bfloat16)
+        Yv = P.View(Y.data, Y.dims, Y.strides, dtype=P.BF16)
+        idx, _ = P.cprand_sample(dims, n, S, 19, 2)
+        W, V = P.cprand_mttkrp_sampled(Yv, n, Ad, R, S, idx)
+        Wr, Vr = OR.bf16_normal_blocks(X, OP.sample_indices(dims, n, S, 19, 2), A, n)
+        close(W.cpu().numpy(), Wr, 1e-5, "BF16 W mode %d" % n)
+        close(V.cpu().numpy(), Vr, 1e-12, "BF16 V mode %d" % n)
+
+
 # --------------------------------------------------------------------------
 # solve and normalise
 @pytest.mark.parametrize("In,R", [(50, 5), (401, 10), (70, 17), (40, 25), (64, 32), (90, 33), (1000, 50), (33, 64)])
@@ -190,15 +210,31 @@ def test_solve_singular_uses_pseudoinverse(R, rk):
 
 
 def test_solve_f32_refinement():
+    """One refinement step: residual of the FP32 normal equations (W_ref,
+    V_ref), corrected with the inverse of the lower-precision V."""
+    from oracle import precision as OR
     rng = _rng(9)
     In, R = 150, 20
     Z = rng.standard_normal((200, R))
-    V = Z.T @ Z
-    W = rng.standard_normal((In, R))
-    Wb = W + 1e-3 * rng.standard_normal((In, R))        # a perturbed first right-hand side
-    A, lam, _ = P.cprand_solve(dev(V), dev(Wb, torch.float32), W_refine=dev(W, torch.float32))
-    ref = np.linalg.solve(V, W.astype(np.float32).astype(np.float64).T).T
-    close(A.cpu().numpy() * lam.cpu().numpy(), ref, 1e-5)
+    V_ref = Z.T @ Z
+    V_lo = V_ref + 1e-3 * np.diag(np.diag(V_ref)) + 1e-4 * (lambda E: E + E.T)(rng.standard_normal((R, R)))
+    W = rng.standard_normal((In, R)).astype(np.float32).astype(np.float64)
+    Wb = (W + 1e-3 * rng.standard_normal((In, R))).astype(np.float32).astype(np.float64)
+    A, lam, _ = P.cprand_solve(dev(V_lo), dev(Wb, torch.float32), W_refine=dev(W, torch.float32),
+                               V_refine=dev(V_ref))
+    A0 = np.linalg.solve(V_lo, Wb.T).T
+    want = OR.refine_step(A0, V_lo, W, V_ref)
+    close(A.cpu().numpy() * lam.cpu().numpy(), want, 1e-5, "refined A")
+    # the step moved A0 most of the way to the FP32 solution
+    star = np.linalg.solve(V_ref, W.T).T
+    assert np.linalg.norm(want - star) < 0.1 * np.linalg.norm(A0 - star)
+
+
+def test_solve_refinement_needs_both_blocks():
+    V = dev(np.eye(3))
+    W = dev(np.ones((4, 3)), torch.float32)
+    with pytest.raises(P.CprandError):
+        P.cprand_solve(V, W, W_refine=W)
 
 
 def test_sampled_step_matches_qr_solution():
