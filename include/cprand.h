@@ -127,6 +127,23 @@ int cprand_mttkrp_sampled(const cprand_tensor *X, int32_t n, const void *const *
                           const int8_t *unmix_signs, void *W, double *V,
                           void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * cprand_mttkrp_sampled without a workspace.  Same arguments, results and
+ * kernels as cprand_mttkrp_sampled for real tensors (F64, F32, BF16; a
+ * mixed C64/C128 tensor returns CPRAND_EUNSUPPORTED).  The partial products
+ * and Gram partials go to a fixed device array of
+ * CPRAND_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until
+ * the process ends; a shape whose partials do not fit returns CPRAND_EINVAL
+ * (the message names the bytes needed).  The call allocates nothing and
+ * clears nothing: the gather overwrites every partial it later reads.  All
+ * calls on one GPU share that GPU's array, so calls that overlap on one GPU
+ * (unordered streams, or threads) race; calls ordered on one stream do not. */
+#define CPRAND_NOALLOC_SCRATCH_BYTES 33554432  /* 32 MiB */
+int cprand_mttkrp_sampled_noalloc(const cprand_tensor *X, int32_t n, const void *const *A,
+                                  int32_t R, int32_t S, const int32_t *idx, const double *w,
+                                  void *W, double *V, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Least-squares solve and normalisation (Alg. 3 solve and normalise steps).
  *

@@ -127,6 +127,21 @@ def cprand_mttkrp_sampled(X, n, A, R, S, idx, w=None, unmix_signs=None, W=None, 
     return W, V
 
 
+def cprand_mttkrp_sampled_noalloc(X, n, A, R, S, idx, w=None, W=None, V=None):
+    """cprand_mttkrp_sampled with the library's fixed scratch array instead of
+    a workspace (real tensors only)."""
+    order = len(X.dims)
+    real = torch.float64 if X.dtype == F64 else torch.float32
+    if W is None:
+        W = torch.empty((X.dims[n], R), dtype=real, device=X.data.device)
+    if V is None:
+        V = torch.empty((R, R), dtype=torch.float64, device=X.data.device)
+    arr = _ptr_array([None if m == n else A[m] for m in range(order)], order)
+    _check(_lib.cprand_mttkrp_sampled_noalloc(C.byref(X.c()), n, arr, R, S, _ptr(idx), _ptr(w), _ptr(W), _ptr(V),
+                                              _stream()))
+    return W, V
+
+
 def cprand_solve(V, W, W_refine=None, V_refine=None, A_out=None, lambda_out=None, info=None, ws=None):
     In, R = W.shape
     dtype = F64 if W.dtype == torch.float64 else F32

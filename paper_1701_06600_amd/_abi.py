@@ -17,6 +17,8 @@ EUNSUPPORTED = -5
 
 F64, F32, BF16, C64, C128 = 0, 1, 2, 3, 4
 
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
 MIX_NONE, MIX_FFT = 0, 1
 PREC_NATIVE, PREC_BF16_REFINE, PREC_BF16 = 0, 1, 2
 PROPOSAL_UNIFORM, PROPOSAL_TABLE, PROPOSAL_LEARNED, PROPOSAL_MARGINAL, PROPOSAL_MIXTURE = 0, 1, 2, 3, 4
@@ -60,6 +62,9 @@ SIGNATURES = [
     ("cprand_mttkrp_sampled", C.c_int, [C.POINTER(cprand_tensor), C.c_int32, C.POINTER(C.c_void_p),
                                         C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("cprand_mttkrp_sampled_noalloc", C.c_int, [C.POINTER(cprand_tensor), C.c_int32, C.POINTER(C.c_void_p),
+                                                C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                C.c_void_p, C.c_void_p]),
     ("cprand_solve", C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                C.c_void_p]),

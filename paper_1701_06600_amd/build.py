@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libcprand.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["sample.hip", "mttkrp.hip", "mttkrp_bf16.hip", "solve.hip", "step.hip", "fit.hip", "fft.hip",
-           "layout.hip", "proposal.hip", "api.cpp", "api_proposal.cpp", "als.cpp"]
+           "layout.hip", "proposal.hip", "noalloc.hip", "api.cpp", "api_proposal.cpp", "als.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # no packed-FP32 instructions in device code

@@ -87,6 +87,21 @@ def test_mttkrp_validation():
                                    C.c_void_p(16), C.c_void_p(16), ws, 1 << 30, None) == P.EINVAL
 
 
+def test_mttkrp_noalloc_validation():
+    """The fixed-scratch entry point rejects, before any HIP call, what the
+    workspace one rejects, mixed tensors, and shapes whose partials exceed
+    its array."""
+    L = P._lib
+    A = (C.c_void_p * 3)(16, 16, 16)
+    args = (C.c_void_p(16), None, C.c_void_p(16), C.c_void_p(16), None)
+    assert L.cprand_mttkrp_sampled_noalloc(C.byref(_tensor()), 0, A, 65, 10, *args) == P.EINVAL
+    assert L.cprand_mttkrp_sampled_noalloc(C.byref(_tensor()), 3, A, 4, 10, *args) == P.EINVAL
+    assert L.cprand_mttkrp_sampled_noalloc(C.byref(_tensor(dtype=_abi.C64)), 0, A, 4, 10, *args) == P.EUNSUPPORTED
+    big = _tensor(dims=(1 << 24, 8, 8))
+    assert L.cprand_mttkrp_sampled_noalloc(C.byref(big), 0, A, 64, 4096, *args) == P.EINVAL
+    assert b"scratch" in L.cprand_last_error()
+
+
 def test_workspace_size_monotone_and_zero_on_bad_args():
     X = _tensor(dims=(400, 400, 400))
     a = P._lib.cprand_workspace_size(C.byref(X), 10, 300, 2 ** 14)
@@ -166,7 +181,7 @@ def test_binding_constants_match_header_defines():
     names = ["MAX_ORDER", "MAX_RANK", "OK", "W_PINV", "W_MAXIT", "W_FALLBACK", "EINVAL", "ENAN", "EHIP",
              "ENOMEM", "EUNSUPPORTED", "F64", "F32", "BF16", "C64", "C128", "MIX_NONE", "MIX_FFT",
              "PREC_NATIVE", "PREC_BF16_REFINE", "PREC_BF16", "PROPOSAL_UNIFORM", "PROPOSAL_TABLE",
-             "PROPOSAL_LEARNED", "PROPOSAL_MARGINAL", "PROPOSAL_MIXTURE"]
+             "PROPOSAL_LEARNED", "PROPOSAL_MARGINAL", "PROPOSAL_MIXTURE", "NOALLOC_SCRATCH_BYTES"]
     for n in names:
         assert n in d, "CPRAND_%s is not #defined in the header" % n
         assert getattr(_abi, n) == d[n], (n, getattr(_abi, n), d[n])
