@@ -216,6 +216,28 @@ int cprand_mix_factor(int32_t I, int32_t R, const void *A, int32_t dtype,
                       const int8_t *signs, void *Ahat, int32_t inverse, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Real mixing for CPRAND-PREMIX (Section 3.3, Alg. 5): with a real orthogonal
+ * F_m the mixed problem stays real, so plain CPRAND runs on the mixed tensor
+ * and its factors are unmixed once at the end.  F_m is the orthonormal
+ * DCT-II, (F_m)[k][i] = s_k cos(pi k (2i + 1) / (2 I_m)), s_0 = sqrt(1/I_m),
+ * s_k = sqrt(2/I_m) for k > 0; the signs D_m are those of cprand_mix.
+ *
+ * cprand_mix_dct: Xhat = X x_0 F_0 D_0 ... x_{N-1} F_{N-1} D_{N-1}.  X is
+ * F32 or F64 with any strides; Xhat is a caller-allocated column-major
+ * tensor of the same dtype and dims that does not overlap X.  signs and
+ * normX_out as for cprand_mix (||Xhat|| = ||X||).  Every I_m must factor
+ * into 2, 3, 5 and 7 and be at most 4096 (F32) or 2048 (F64); otherwise
+ * CPRAND_EUNSUPPORTED.  workspace: 32768 bytes.
+ *
+ * cprand_mix_factor_dct: A-hat = F D A for one I x R row-major real factor
+ * (dtype F32 or F64; A and out do not overlap); with inverse != 0, A =
+ * D F^T A-hat (the unmix of Alg. 5).  Sums in FP64. */
+int cprand_mix_dct(const cprand_tensor *X, uint64_t seed, const cprand_tensor *Xhat, int8_t *signs,
+                   double *normX_out, void *workspace, size_t workspace_bytes, void *stream);
+int cprand_mix_factor_dct(int32_t I, int32_t R, const void *A, int32_t dtype, const int8_t *signs, void *out,
+                          int32_t inverse, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Layout: a copy of X with mode n innermost (its mode-n fibers contiguous,
  * each padded to ld elements), optionally converted to BF16 (round to
  * nearest even) or between real types.  Y->dims must equal X->dims;
@@ -286,6 +308,7 @@ int cprand_mlp_train(float *params, const float *X, const float *t, const int64_
  */
 #define CPRAND_MIX_NONE 0
 #define CPRAND_MIX_FFT 1
+#define CPRAND_MIX_DCT 2   /* CPRAND-PREMIX: real DCT-II mixing, plain CPRAND on the mixed tensor */
 
 #define CPRAND_PREC_NATIVE 0       /* arithmetic in the tensor's own type (F64 or F32) */
 #define CPRAND_PREC_BF16_REFINE 1  /* BF16 products, FP64 solve, FP32 refinement (see refine_every) */

@@ -16,7 +16,7 @@ import math
 import torch
 
 from . import _abi
-from ._abi import (BF16, C64, C128, EHIP, EINVAL, ENAN, ENOMEM, EUNSUPPORTED, F32, F64, MIX_FFT,
+from ._abi import (BF16, C64, C128, EHIP, EINVAL, ENAN, ENOMEM, EUNSUPPORTED, F32, F64, MIX_DCT, MIX_FFT,
                    MIX_NONE, OK, PREC_BF16, PREC_BF16_REFINE, PREC_NATIVE, PROPOSAL_LEARNED,
                    PROPOSAL_MARGINAL, PROPOSAL_MIXTURE, PROPOSAL_TABLE, PROPOSAL_UNIFORM, W_FALLBACK,
                    W_MAXIT, W_PINV)
@@ -208,6 +208,31 @@ def cprand_mix_factor(A, signs, inverse=False, out=None):
         if out is None:
             out = torch.empty((I, R), dtype=torch.float64 if dtype == F64 else torch.float32, device=A.device)
     _check(_lib.cprand_mix_factor(I, R, _ptr(A), dtype, _ptr(signs), _ptr(out), 1 if inverse else 0, _stream()))
+    return out
+
+
+def cprand_mix_dct(X, seed, Xhat=None, signs=None, normX=None, ws=None):
+    dev = X.data.device
+    P = math.prod(X.dims)
+    if Xhat is None:
+        Xhat = View(torch.empty(P, dtype=X.data.dtype, device=dev), X.dims)
+    if signs is None:
+        signs = torch.empty(sum(X.dims), dtype=torch.int8, device=dev)
+    if normX is None:
+        normX = torch.empty(1, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = torch.empty(4096 * 8, dtype=torch.uint8, device=dev)
+    _check(_lib.cprand_mix_dct(C.byref(X.c()), C.c_uint64(seed), C.byref(Xhat.c()), _ptr(signs), _ptr(normX),
+                               _ptr(ws), ws.numel(), _stream()))
+    return Xhat, signs, normX
+
+
+def cprand_mix_factor_dct(A, signs, inverse=False, out=None):
+    I, R = A.shape
+    dtype = F64 if A.dtype == torch.float64 else F32
+    if out is None:
+        out = torch.empty_like(A)
+    _check(_lib.cprand_mix_factor_dct(I, R, _ptr(A), dtype, _ptr(signs), _ptr(out), 1 if inverse else 0, _stream()))
     return out
 
 

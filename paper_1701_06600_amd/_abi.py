@@ -19,7 +19,7 @@ F64, F32, BF16, C64, C128 = 0, 1, 2, 3, 4
 
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
-MIX_NONE, MIX_FFT = 0, 1
+MIX_NONE, MIX_FFT, MIX_DCT = 0, 1, 2
 PREC_NATIVE, PREC_BF16_REFINE, PREC_BF16 = 0, 1, 2
 PROPOSAL_UNIFORM, PROPOSAL_TABLE, PROPOSAL_LEARNED, PROPOSAL_MARGINAL, PROPOSAL_MIXTURE = 0, 1, 2, 3, 4
 
@@ -74,6 +74,10 @@ SIGNATURES = [
     ("cprand_norm", C.c_int, [C.POINTER(cprand_tensor), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("cprand_mix", C.c_int, [C.POINTER(cprand_tensor), C.c_uint64, C.POINTER(cprand_tensor), C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("cprand_mix_dct", C.c_int, [C.POINTER(cprand_tensor), C.c_uint64, C.POINTER(cprand_tensor), C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("cprand_mix_factor_dct", C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_int32, C.c_void_p]),
     ("cprand_mix_factor", C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_int32, C.c_void_p]),
     ("cprand_mode_major_strides", C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.c_int32, C.c_int64,

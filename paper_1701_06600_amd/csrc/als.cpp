@@ -67,6 +67,12 @@ struct cprand_plan {
     int xkind = 0;
     int64_t P = 1;
     bool dbl = false, mix = false, bf16 = false, refine = false;
+    // CPRAND-PREMIX: the loop runs plain CPRAND on xdct, the real DCT-mixed
+    // tensor (column-major); istrides are the strides of the tensor the loop
+    // iterates on (X's own, or xdct's)
+    bool premix = false;
+    void *xdct = nullptr;
+    int64_t istrides[CPRAND_MAX_ORDER] = {};
     // BF16 form with refinement: whether the current iterations refine (all
     // of them with refine_every; else from the first stop-rule hit on)
     bool ref_now = true;
@@ -198,7 +204,7 @@ FitArgs fit_args(const cprand_plan *p, const void *xdata) {
     fa.mi.order = N;
     for (int m = 0; m < N; ++m) {
         fa.mi.dims[m] = p->dims[m];
-        fa.mi.strides[m] = p->xstrides[m];
+        fa.mi.strides[m] = p->istrides[m];
         fa.A.p[m] = p->mix ? p->fhat[m] : p->fac[m];
     }
     if (p->mix) {
@@ -494,41 +500,45 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     if (o.S < 1) return set_error(CPRAND_EINVAL, "S = %d < 1", o.S);
     if (o.P_hat < 1) return set_error(CPRAND_EINVAL, "P_hat = %d < 1", o.P_hat);
     if (o.max_iters < 1) return set_error(CPRAND_EINVAL, "max_iters = %d < 1", o.max_iters);
-    if (o.mix != CPRAND_MIX_NONE && o.mix != CPRAND_MIX_FFT) return set_error(CPRAND_EINVAL, "mix = %d", o.mix);
+    if (o.mix != CPRAND_MIX_NONE && o.mix != CPRAND_MIX_FFT && o.mix != CPRAND_MIX_DCT)
+        return set_error(CPRAND_EINVAL, "mix = %d", o.mix);
+    const bool cmix = o.mix == CPRAND_MIX_FFT;  // complex mixing (CPRAND-MIX)
     if (o.precision < 0 || o.precision > 2) return set_error(CPRAND_EINVAL, "precision = %d", o.precision);
     if (o.precision != CPRAND_PREC_NATIVE && xk != K_F32)
         return set_error(CPRAND_EINVAL, "the BF16 form reads an F32 tensor");
-    if (o.precision != CPRAND_PREC_NATIVE && o.mix) return set_error(CPRAND_EUNSUPPORTED, "BF16 with mixing");
+    if (o.precision != CPRAND_PREC_NATIVE && cmix) return set_error(CPRAND_EUNSUPPORTED, "BF16 with FFT mixing");
     if (o.proposal == CPRAND_PROPOSAL_TABLE) {
         if (!o.proposal_cdf) return set_error(CPRAND_EINVAL, "PROPOSAL_TABLE needs proposal_cdf");
         for (int m = 0; m < X->order; ++m)
             if (!o.proposal_cdf[m]) return set_error(CPRAND_EINVAL, "proposal_cdf[%d] is NULL", m);
-        if (o.mix) return set_error(CPRAND_EUNSUPPORTED, "importance sampling with mixing");
+        if (cmix) return set_error(CPRAND_EUNSUPPORTED, "importance sampling with FFT mixing");
     } else if (o.proposal == CPRAND_PROPOSAL_LEARNED || o.proposal == CPRAND_PROPOSAL_MARGINAL) {
         if (o.proposal == CPRAND_PROPOSAL_LEARNED && !o.mlp_params)
             return set_error(CPRAND_EINVAL, "PROPOSAL_LEARNED needs mlp_params");
         if (xk != K_F32) return set_error(CPRAND_EUNSUPPORTED, "adaptive proposals read FP32 factors");
-        if (o.mix) return set_error(CPRAND_EUNSUPPORTED, "importance sampling with mixing");
+        if (cmix) return set_error(CPRAND_EUNSUPPORTED, "importance sampling with FFT mixing");
         if (!(o.alpha >= 0.0 && o.alpha <= 1.0)) return set_error(CPRAND_EINVAL, "alpha outside [0, 1]");
     } else if (o.proposal != CPRAND_PROPOSAL_UNIFORM) {
         return set_error(CPRAND_EINVAL, "proposal %d", o.proposal);
     }
-    if (o.mix && !is_colmajor(X)) return set_error(CPRAND_EUNSUPPORTED, "mixing needs a column-major X");
+    if (cmix && !is_colmajor(X)) return set_error(CPRAND_EUNSUPPORTED, "FFT mixing needs a column-major X");
     cprand_plan *p = new cprand_plan();
     p->o = o;
     p->N = X->order;
     p->xkind = xk;
     p->dbl = xk == K_F64;
-    p->mix = o.mix == CPRAND_MIX_FFT;
+    p->mix = cmix;
+    p->premix = o.mix == CPRAND_MIX_DCT;
     p->bf16 = o.precision != CPRAND_PREC_NATIVE;
     p->refine = o.precision == CPRAND_PREC_BF16_REFINE;
     for (int m = 0; m < p->N; ++m) {
         p->dims[m] = X->dims[m];
         p->xstrides[m] = X->strides[m];
+        p->istrides[m] = p->premix ? p->P : X->strides[m];
         p->P *= X->dims[m];
     }
     const int N = p->N, R = o.R;
-    if (p->mix) {
+    if (p->mix || p->premix) {
         for (int m = 0; m < N; ++m) {
             hipError_t fe;
             if (!fft_plan_get(p->dims[m], p->dbl, &fe)) {
@@ -585,14 +595,14 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
             View &v = p->bf16 ? p->rview[n] : p->gview[n];
             if (p->bf16 && !p->refine) continue;
             const int ve = vec_elems(xk);
-            bool ok = o.layout == 1 || X->strides[n] == 1;
+            bool ok = o.layout == 1 || p->istrides[n] == 1;
             for (int m = 0; m < N && ok && o.layout != 1; ++m)
-                if (m != n && X->strides[m] % ve) ok = false;
+                if (m != n && p->istrides[m] % ve) ok = false;
             if (ok) {
                 v.kind = xk;
-                for (int m = 0; m < N; ++m) v.strides[m] = X->strides[m];
+                for (int m = 0; m < N; ++m) v.strides[m] = p->istrides[m];
             } else {
-                if (!is_colmajor(X)) {
+                if (!p->premix && !is_colmajor(X)) {
                     delete p;
                     return set_error(CPRAND_EUNSUPPORTED, "layout copies read a column-major X");
                 }
@@ -600,6 +610,7 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
             }
         }
     }
+    if (e == hipSuccess && p->premix) e = dalloc(p, &p->xdct, (size_t)p->P * tsz);
     if (e == hipSuccess) {
         int64_t tot = 0;
         for (int m = 0; m < N; ++m) tot += p->dims[m];
@@ -725,14 +736,18 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
     const int N = p->N, R = p->o.R;
     const size_t tsz = p->dbl ? 8 : 4;
     hipError_t e = hipSuccess;
+    // the real tensor the loop iterates on: X, or its DCT-mixed copy
+    const void *xit = p->premix ? p->xdct : X->data;
+    ModeInfo xit_i = mode_info(X, 0);
+    for (int m = 0; m < N; ++m) xit_i.strides[m] = p->istrides[m];
     bool contig_x[CPRAND_MAX_ORDER];
     for (int n = 0; n < N; ++n) {
         const View &v = p->mix ? p->gview[n] : (p->bf16 ? p->rview[n] : p->gview[n]);
-        contig_x[n] = fibers_vectorizable(p->mix ? p->xhat : X->data, p->mix ? p->gkind : p->xkind, v.strides, N, n);
+        contig_x[n] = fibers_vectorizable(p->mix ? p->xhat : xit, p->mix ? p->gkind : p->xkind, v.strides, N, n);
     }
 
     e = hipEventRecord(p->ev[0], st);
-    for (int m = 1; m < N && e == hipSuccess; ++m)
+    for (int m = 1; m < N && e == hipSuccess && !p->premix; ++m)
         e = hipMemcpyAsync(p->fac[m], A_inout[m], (size_t)p->dims[m] * R * tsz, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = launch_fill_u64(p->t_dev, 0, st);
     if (e == hipSuccess) e = launch_fill_u64((uint64_t *)p->info, 0, st);
@@ -796,13 +811,29 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
                                           p->fhat[m], false, st);
         }
     } else if (e == hipSuccess) {
+        if (p->premix) {
+            // CPRAND-PREMIX (Alg. 5): mix X once with the real DCT, and the
+            // initial factors with it, then iterate on the mixed tensor
+            e = launch_signs(xi, p->o.seed, p->signs, st);
+            for (int m = 0; m < N && e == hipSuccess; ++m) {
+                e = hipEventRecord(tev[2 + 2 * m], st);
+                if (e == hipSuccess)
+                    e = launch_dct_pass(m == 0 ? xi : xit_i, X->data, p->xkind, p->xdct, p->dbl, m, m == 0, p->signs,
+                                        st);
+                if (e == hipSuccess) e = hipEventRecord(tev[3 + 2 * m], st);
+                timed_mix[m] = e == hipSuccess;
+            }
+            for (int m = 1; m < N && e == hipSuccess; ++m)
+                e = launch_factor_dct((int32_t)p->dims[m], R, A_inout[m], p->signs + p->seg_off[m], p->fac[m], p->dbl,
+                                      false, st);
+        }
         for (int n = 0; n < N && e == hipSuccess; ++n) {
             const bool any = p->gview[n].own || (p->refine && p->rview[n].own);
             if (any) e = hipEventRecord(tev[2 + 2 * N + 2 * n], st);
             if (e == hipSuccess && p->gview[n].own)
-                e = launch_layout_copy(xi, X->data, p->xkind, n, p->gview[n].ld, p->gview[n].data, p->gview[n].kind, st);
+                e = launch_layout_copy(xit_i, xit, p->xkind, n, p->gview[n].ld, p->gview[n].data, p->gview[n].kind, st);
             if (e == hipSuccess && p->refine && p->rview[n].own)
-                e = launch_layout_copy(xi, X->data, p->xkind, n, p->rview[n].ld, p->rview[n].data, p->rview[n].kind, st);
+                e = launch_layout_copy(xit_i, xit, p->xkind, n, p->rview[n].ld, p->rview[n].data, p->rview[n].kind, st);
             if (any && e == hipSuccess) e = hipEventRecord(tev[3 + 2 * N + 2 * n], st);
             timed_lay[n] = any && e == hipSuccess;
         }
@@ -828,7 +859,7 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
                               p->o.proposal == CPRAND_PROPOSAL_TABLE ? &cdf : nullptr, p->pre_idx, p->pre_w, st);
     }
     // the fixed fit set: rows and tensor values drawn once per run
-    if (e == hipSuccess) e = launch_fit_set(fit_args(p, X->data), p->frow, p->fx, st);
+    if (e == hipSuccess) e = launch_fit_set(fit_args(p, xit), p->frow, p->fx, st);
     if (e == hipSuccess) e = hipEventRecord(p->ev[1], st);
     if (e != hipSuccess) return hip_fail(e, "setup");
 
@@ -856,7 +887,7 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
             p->ref_now = k == 1;
             e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed);
             if (e == hipSuccess) {
-                hipError_t e2 = enqueue_iteration(p, X->data, contig_x, p->cap);
+                hipError_t e2 = enqueue_iteration(p, xit, contig_x, p->cap);
                 e = hipStreamEndCapture(p->cap, &graphs[k]);
                 if (e2 != hipSuccess) e = e2;
             }
@@ -913,7 +944,7 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
         return launch_fill_u64((uint64_t *)p->alpha_dev, bits, st);
     };
     auto run_iteration = [&]() {
-        hipError_t r = graphed ? hipGraphLaunch(cur_exec(), st) : enqueue_iteration(p, X->data, contig_x, st);
+        hipError_t r = graphed ? hipGraphLaunch(cur_exec(), st) : enqueue_iteration(p, xit, contig_x, st);
         if (r == hipSuccess) r = hipEventRecord(p->ev[2], st);
         if (r == hipSuccess) r = hipEventSynchronize(p->ev[2]);
         return r;
@@ -936,7 +967,7 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
                 if (r == hipSuccess) r = hipEventRecord(p->ev[t & 1 ? 3 : 2], st);
             } else {
                 const IterCtl ic{(uint64_t)t, p->fst, p->ev_state[t & 1]};
-                r = enqueue_iteration(p, X->data, contig_x, st, &ic);
+                r = enqueue_iteration(p, xit, contig_x, st, &ic);
                 if (r == hipSuccess) r = hipEventRecord(p->ev[t & 1 ? 3 : 2], p->fst);
             }
             return r;
@@ -1063,8 +1094,11 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
     }
     if (e != hipSuccess) return hip_fail(e, "final unmix");
     hipEventRecord(p->ev[3], st);
+    // CPRAND-PREMIX: A = D_m F_m^T A-hat (Alg. 5, final unmix)
     for (int m = 0; m < N && e == hipSuccess; ++m)
-        e = hipMemcpyAsync(A_inout[m], p->fac[m], (size_t)p->dims[m] * R * tsz, hipMemcpyDeviceToDevice, st);
+        e = p->premix ? launch_factor_dct((int32_t)p->dims[m], R, p->fac[m], p->signs + p->seg_off[m], A_inout[m], p->dbl,
+                                          true, st)
+                      : hipMemcpyAsync(A_inout[m], p->fac[m], (size_t)p->dims[m] * R * tsz, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(lambda_out, p->lambda, (size_t)R * 8, hipMemcpyDeviceToDevice, st);
     int32_t info = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&info, p->info, 4, hipMemcpyDeviceToHost, st);

@@ -393,6 +393,52 @@ int cprand_mix_factor(int32_t I, int32_t R, const void *A, int32_t dtype, const 
     return e == hipSuccess ? CPRAND_OK : hip_fail(e, "cprand_mix_factor");
 }
 
+int cprand_mix_dct(const cprand_tensor *X, uint64_t seed, const cprand_tensor *Xhat, int8_t *signs,
+                   double *normX_out, void *workspace, size_t workspace_bytes, void *stream) {
+    g_last_error.clear();
+    int rc = check_tensor(X, "X");
+    if (rc) return rc;
+    rc = check_tensor(Xhat, "Xhat");
+    if (rc) return rc;
+    const int xk = kind_of(X->dtype);
+    if (xk != K_F32 && xk != K_F64) return set_error(CPRAND_EINVAL, "X must be F32 or F64");
+    if (Xhat->dtype != X->dtype) return set_error(CPRAND_EINVAL, "Xhat must have the dtype of X");
+    if (Xhat->order != X->order) return set_error(CPRAND_EINVAL, "Xhat order differs");
+    for (int m = 0; m < X->order; ++m)
+        if (Xhat->dims[m] != X->dims[m]) return set_error(CPRAND_EINVAL, "Xhat dims differ");
+    if (!is_colmajor(Xhat)) return set_error(CPRAND_EUNSUPPORTED, "Xhat must be column-major");
+    if (!signs || !normX_out) return set_error(CPRAND_EINVAL, "signs and normX_out must be non-NULL");
+    if (!workspace || workspace_bytes < 4096 * 8) return set_error(CPRAND_EINVAL, "workspace of 32768 bytes needed");
+    const bool dbl = xk == K_F64;
+    for (int m = 0; m < X->order; ++m) {
+        hipError_t fe;
+        if (!fft_plan_get(X->dims[m], dbl, &fe))
+            return set_error(CPRAND_EUNSUPPORTED, "mode %d length %lld: not {2,3,5,7}-smooth or too long", m,
+                             (long long)X->dims[m]);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const ModeInfo xi = mode_info(X, 0), hi = mode_info(Xhat, 0);
+    hipError_t e = launch_signs(xi, seed, signs, st);
+    for (int m = 0; m < X->order && e == hipSuccess; ++m)
+        e = launch_dct_pass(m == 0 ? xi : hi, X->data, xk, Xhat->data, dbl, m, m == 0, signs, st);
+    if (e == hipErrorInvalidValue) return set_error(CPRAND_EUNSUPPORTED, "a mode is too long for the DCT tile");
+    int32_t np = 0;
+    if (e == hipSuccess) e = launch_normsq_partial(xi, X->data, xk, (double *)workspace, &np, st);
+    if (e == hipSuccess) e = launch_sqrt_sum((double *)workspace, np, normX_out, st);
+    return e == hipSuccess ? CPRAND_OK : hip_fail(e, "cprand_mix_dct");
+}
+
+int cprand_mix_factor_dct(int32_t I, int32_t R, const void *A, int32_t dtype, const int8_t *signs, void *out,
+                          int32_t inverse, void *stream) {
+    g_last_error.clear();
+    if (I < 1 || R < 1 || R > CPRAND_MAX_RANK) return set_error(CPRAND_EINVAL, "bad sizes I=%d R=%d", I, R);
+    if (dtype != CPRAND_F32 && dtype != CPRAND_F64) return set_error(CPRAND_EINVAL, "dtype must be F32 or F64");
+    if (!A || !signs || !out) return set_error(CPRAND_EINVAL, "NULL pointer argument");
+    if (A == out) return set_error(CPRAND_EINVAL, "A and out must not overlap");
+    hipError_t e = launch_factor_dct(I, R, A, signs, out, dtype == CPRAND_F64, inverse != 0, (hipStream_t)stream);
+    return e == hipSuccess ? CPRAND_OK : hip_fail(e, "cprand_mix_factor_dct");
+}
+
 int cprand_mode_major_strides(int32_t order, const int64_t *dims, int32_t n, int64_t ld, int64_t *strides_out) {
     g_last_error.clear();
     if (order < 2 || order > CPRAND_MAX_ORDER || !dims || !strides_out || n < 0 || n >= order)

@@ -1,0 +1,280 @@
+// Real orthogonal mixing for CPRAND-PREMIX (Section 3.3, Alg. 5): the
+// orthonormal DCT-II, C[k][i] = s_k cos(pi k (2i + 1) / (2L)) with s_0 =
+// sqrt(1/L) and s_k = sqrt(2/L), applied along every mode of a real tensor
+// after the random signs, and the matching mix and unmix of factor matrices.
+//
+// Tensor passes compute the DCT through one complex FFT of the same length
+// (Makhoul, "A fast cosine transform in one and multiple dimensions", IEEE
+// TASSP 1980): with v[n] = x[2n] and v[L-1-n] = x[2n+1],
+//   sum_i x[i] cos(pi k (2i + 1) / (2L)) = Re(exp(-i pi k / (2L)) V[k]),
+// V the unnormalised DFT of v.  Two real fibers share one complex FFT (one
+// in the real, one in the imaginary part of z); their spectra separate by
+// conjugate symmetry, V1[k] = (Z[k] + conj Z[L-k]) / 2 and V2[k] = (Z[k] -
+// conj Z[L-k]) / (2i).  The FFT stages are those of the CPRAND-MIX passes.
+// Each pass reads and writes 1 real element per element of the tensor.
+#include <math.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+#include "fft_device.hpp"
+
+namespace cprand {
+
+// Post-rotation table of one length: (s_k cos(pi k/(2L)), s_k sin(pi k/(2L)))
+// for k < L, computed on the host in FP64; cached per (device, L, precision).
+static const void *dct_table_get(int64_t L, bool dbl, hipError_t *err) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int64_t, int>, void *> cache;
+    *err = hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *err = e;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_tuple(dev, L, dbl ? 1 : 0);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const size_t esz = dbl ? 16 : 8;
+    std::vector<unsigned char> host(esz * L);
+    for (int64_t k = 0; k < L; ++k) {
+        const double s = k == 0 ? sqrt(1.0 / (double)L) : sqrt(2.0 / (double)L);
+        const double a = M_PI * (double)k / (2.0 * (double)L);
+        const double c = s * cos(a), sn = s * sin(a);
+        if (dbl) {
+            ((double *)host.data())[2 * k] = c;
+            ((double *)host.data())[2 * k + 1] = sn;
+        } else {
+            ((float *)host.data())[2 * k] = (float)c;
+            ((float *)host.data())[2 * k + 1] = (float)sn;
+        }
+    }
+    void *d = nullptr;
+    e = hipMalloc(&d, esz * L);
+    if (e == hipSuccess) e = hipMemcpy(d, host.data(), esz * L, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        *err = e;
+        return nullptr;
+    }
+    cache[key] = d;
+    return d;
+}
+
+// One DCT-II pass along mode m over a tile of 2 TC real fibers.  The tensor
+// Y is column-major [J][L][K] (J = product of the dims before m, K after);
+// fiber q is (j = q % J, k = q / J), element l at j + J L k + J l.  FIRST
+// (m = 0): read X through its own strides, multiply by the product of every
+// mode's signs and write Y; otherwise Y is transformed in place.  LC > 0:
+// compile-time length (in-place Stockham stages, one LDS tile), else the
+// run-time radix schedule of fp (two tiles).
+template <typename T, typename Tin, int LC, int TC, int NT, bool FIRST>
+__global__ __launch_bounds__(NT) void dct_pass_kernel(FftPlan fp, const Tin *X, T *Y, int64_t J, int64_t K,
+                                                      ModeInfo xi, int m, const int8_t *signs, const cx<T> *twg,
+                                                      const cx<T> *csg) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr int FC = 2 * TC;
+    const int L = LC > 0 ? LC : (int)fp.L;
+    const int ldt = TC + 1;
+    cx<T> *b0 = (cx<T> *)lds;
+    cx<T> *b1 = LC > 0 ? b0 : b0 + L * ldt;
+    cx<T> *tw = b1 + L * ldt;
+    cx<T> *cs = tw + L;
+    __shared__ int64_t cout[FC];
+    __shared__ int64_t cin[FIRST ? FC : 1];
+    __shared__ T csign[FIRST ? FC : 1];
+    const int tid = threadIdx.x;
+    const int64_t ncols = J * K;
+    const int64_t q0 = (int64_t)blockIdx.x * FC;
+    const int nc = (int)min((int64_t)FC, ncols - q0);
+    for (int e = tid; e < L; e += NT) {
+        tw[e] = twg[e];
+        cs[e] = csg[e];
+    }
+    for (int c = tid; c < FC; c += NT) {
+        if (c >= nc) continue;
+        const int64_t q = q0 + c;
+        const int64_t j = q % J, k = q / J;
+        cout[c] = j + J * L * k;
+        if (FIRST) {  // m = 0: q runs over modes 1 .. order-1
+            int64_t r = q, off = 0;
+            T sg = (T)1;
+            int soff = (int)xi.dims[0];
+            for (int mm = 1; mm < xi.order; ++mm) {
+                const int64_t im = r % xi.dims[mm];
+                r /= xi.dims[mm];
+                off += im * xi.strides[mm];
+                sg *= (T)signs[soff + im];
+                soff += (int)xi.dims[mm];
+            }
+            cin[c] = off;
+            csign[c] = sg;
+        }
+    }
+    __syncthreads();
+    // fiber c -> real (even c) or imaginary (odd c) part of column c / 2, in
+    // Makhoul's order; fibers past the end contribute zeros
+    for (int e = tid; e < L * FC; e += NT) {
+        int l, c;
+        if (J == 1) {
+            c = e / L;
+            l = e - c * L;
+        } else {
+            l = e / FC;
+            c = e - l * FC;
+        }
+        T v = (T)0;
+        if (c < nc) {
+            if (FIRST)
+                v = (T)X[cin[c] + xi.strides[0] * (int64_t)l] * csign[c] * (T)signs[l];
+            else
+                v = Y[cout[c] + J * (int64_t)l];
+        }
+        const int p = (l & 1) ? (L - 1 - (l >> 1)) : (l >> 1);
+        ((T *)&b0[p * ldt + (c >> 1)])[c & 1] = v;
+    }
+    __syncthreads();
+    cx<T> *res;
+    if constexpr (LC > 0) {
+        fft_ct<T, LC, TC, NT, -1>(b0, tw);
+        res = b0;
+    } else {
+        res = fft_tile_rt<T, -1>(b0, b1, fp, ldt, TC, tw);
+    }
+    for (int e = tid; e < L * FC; e += NT) {
+        int k, c;
+        if (J == 1) {
+            c = e / L;
+            k = e - c * L;
+        } else {
+            k = e / FC;
+            c = e - k * FC;
+        }
+        if (c >= nc) continue;
+        const int cc = c >> 1, mk = k == 0 ? 0 : L - k;
+        const cx<T> zk = res[k * ldt + cc], zm = res[mk * ldt + cc];
+        T a, b;
+        if (c & 1) {  // V2 = (Z[k] - conj Z[L-k]) / (2i)
+            a = zk.im + zm.im;
+            b = zm.re - zk.re;
+        } else {      // V1 = (Z[k] + conj Z[L-k]) / 2
+            a = zk.re + zm.re;
+            b = zk.im - zm.im;
+        }
+        const cx<T> w = cs[k];
+        Y[cout[c] + J * (int64_t)k] = (T)0.5 * (w.re * a + w.im * b);
+    }
+}
+
+template <typename T, typename Tin, int LC, int TC, int NT>
+static hipError_t launch_dct_tiles(const FftPlan *fp, const void *tab, const ModeInfo &xi, const void *X, void *Y,
+                                     int m, bool first, const int8_t *signs, int64_t J, int64_t K, hipStream_t st) {
+    const int64_t L = fp->L;
+    const size_t lds = ((LC > 0 ? 1 : 2) * (size_t)L * (TC + 1) + 2 * (size_t)L) * sizeof(cx<T>);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const int64_t nb = ceil_div(J * K, 2 * TC);
+    if (first)
+        hipLaunchKernelGGL((dct_pass_kernel<T, Tin, LC, TC, NT, true>), dim3((unsigned)nb), dim3(NT), lds, st, *fp,
+                           (const Tin *)X, (T *)Y, J, K, xi, m, signs, (const cx<T> *)fp->tw, (const cx<T> *)tab);
+    else
+        hipLaunchKernelGGL((dct_pass_kernel<T, T, LC, TC, NT, false>), dim3((unsigned)nb), dim3(NT), lds, st, *fp,
+                           (const T *)nullptr, (T *)Y, J, K, xi, m, signs, (const cx<T> *)fp->tw, (const cx<T> *)tab);
+    return hipGetLastError();
+}
+
+// Run-time length: the widest tile (16, 4 or 1 column pairs) whose LDS
+// stays within 64 KB, or within 160 KB for one column pair.
+template <typename T, typename Tin>
+static hipError_t launch_dct_generic(const FftPlan *fp, const void *tab, const ModeInfo &xi, const void *X, void *Y,
+                                     int m, bool first, const int8_t *signs, int64_t J, int64_t K, hipStream_t st) {
+    const size_t per = 2 * (size_t)fp->L * sizeof(cx<T>);
+    auto lds = [&](int tc) { return per * (tc + 1) + per; };
+    if (lds(16) <= 65536)
+        return launch_dct_tiles<T, Tin, 0, 16, 256>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+    if (lds(4) <= 65536)
+        return launch_dct_tiles<T, Tin, 0, 4, 256>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+    return launch_dct_tiles<T, Tin, 0, 1, 256>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+}
+
+hipError_t launch_dct_pass(const ModeInfo &xi, const void *X, int xkind, void *Y, bool dbl, int32_t m, bool first,
+                           const int8_t *signs, hipStream_t st) {
+    if (first && m != 0) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    const FftPlan *fp = fft_plan_get(xi.dims[m], dbl, &e);
+    if (!fp) return e == hipSuccess ? hipErrorInvalidValue : e;
+    const void *tab = dct_table_get(xi.dims[m], dbl, &e);
+    if (!tab) return e;
+    int64_t J = 1, K = 1;
+    for (int i = 0; i < m; ++i) J *= xi.dims[i];
+    for (int i = m + 1; i < xi.order; ++i) K *= xi.dims[i];
+    if (dbl) {
+        if (first && xkind != K_F64) return hipErrorInvalidValue;
+        return launch_dct_generic<double, double>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+    }
+    if (first && xkind == K_F64) return launch_dct_generic<float, double>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+    if (first && xkind != K_F32) return hipErrorInvalidValue;
+    switch (fp->L) {  // compile-time schedules for the common lengths
+        case 60: return launch_dct_tiles<float, float, 60, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+        case 150: return launch_dct_tiles<float, float, 150, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+        case 400: return launch_dct_tiles<float, float, 400, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+        default: return launch_dct_generic<float, float>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Factor mix A-hat = C D A (inverse: A = D C^T A-hat) for one I x R row-major
+// matrix, as a direct product with the DCT matrix (I^2 R multiply-adds, FP64
+// sums; a one-time step per mode).  One workgroup per output row; the row's
+// DCT coefficients are formed in LDS in chunks, the argument reduced exactly
+// as k (2i + 1) mod 4I before cospi.
+template <typename T>
+__global__ __launch_bounds__(256) void factor_dct_kernel(const T *in, const int8_t *sign, T *out, int I, int R,
+                                                         int inverse) {
+    constexpr int kChunk = 4096;
+    __shared__ double coef[kChunk];
+    __shared__ double part[4][64];
+    const int tid = threadIdx.x, row = blockIdx.x;
+    const int r = tid & 63, g = tid >> 6;
+    const double s0 = sqrt(1.0 / (double)I), s1 = sqrt(2.0 / (double)I);
+    double acc = 0.0;
+    for (int j0 = 0; j0 < I; j0 += kChunk) {
+        const int n = min(kChunk, I - j0);
+        __syncthreads();
+        for (int jj = tid; jj < n; jj += 256) {
+            const int j = j0 + jj;
+            const int k = inverse ? j : row, i = inverse ? row : j;
+            const int64_t a = ((int64_t)k * (2 * (int64_t)i + 1)) % (4 * (int64_t)I);
+            double c = (k == 0 ? s0 : s1) * cospi((double)a / (2.0 * (double)I));
+            if (!inverse) c *= (double)sign[i];
+            coef[jj] = c;
+        }
+        __syncthreads();
+        if (r < R)
+            for (int jj = g; jj < n; jj += 4) acc += coef[jj] * (double)in[(int64_t)(j0 + jj) * R + r];
+    }
+    part[g][r] = acc;
+    __syncthreads();
+    if (tid < R) {
+        double v = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+        if (inverse) v *= (double)sign[row];
+        out[(int64_t)row * R + tid] = (T)v;
+    }
+}
+
+hipError_t launch_factor_dct(int32_t I, int32_t R, const void *in, const int8_t *sign, void *out, bool dbl,
+                             bool inverse, hipStream_t st) {
+    if (R < 1 || R > 64 || I < 1) return hipErrorInvalidValue;
+    if (dbl)
+        hipLaunchKernelGGL(factor_dct_kernel<double>, dim3(I), dim3(256), 0, st, (const double *)in, sign,
+                           (double *)out, I, R, inverse ? 1 : 0);
+    else
+        hipLaunchKernelGGL(factor_dct_kernel<float>, dim3(I), dim3(256), 0, st, (const float *)in, sign,
+                           (float *)out, I, R, inverse ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace cprand

@@ -105,6 +105,18 @@ hipError_t launch_mix_pass(const FftPlan *fp, bool dbl, const ModeInfo &xi, cons
                            MixExtras *ex, hipStream_t st);
 hipError_t launch_signs(const ModeInfo &mi, uint64_t seed, int8_t *signs, hipStream_t st);
 
+// ---- real orthogonal mixing (CPRAND-PREMIX) ------------------------------------------
+// One orthonormal DCT-II pass along mode m of a real tensor (dct.hip).  first
+// (m = 0 only): read X (kind xkind, any strides), apply every mode's signs and
+// write the column-major real tensor Y (double when dbl, else float);
+// otherwise transform Y in place.  hipErrorInvalidValue when the length is
+// not {2,3,5,7}-smooth or its tile does not fit in LDS.
+hipError_t launch_dct_pass(const ModeInfo &xi, const void *X, int xkind, void *Y, bool dbl, int32_t m, bool first,
+                           const int8_t *signs, hipStream_t st);
+// A-hat = C D A (inverse: A = D C^T A-hat) for one I x R row-major factor; in != out.
+hipError_t launch_factor_dct(int32_t I, int32_t R, const void *in, const int8_t *sign, void *out, bool dbl,
+                             bool inverse, hipStream_t st);
+
 // ---- solve / normalise -------------------------------------------------------------
 struct SolveArgs {
     int32_t In, R;
