@@ -103,9 +103,9 @@ def main():
         return
 
     def opts(mix, max_iters=w.max_iters):
+        kind = P.MIX_FFT if mix is True else (P.MIX_NONE if mix is False else mix)
         return P.make_opts(R, S, P_hat=w.P_hat, max_iters=max_iters, seed=w.seed, tol=w.tol,
-                           fit_target=w.fit_target, mix=P.MIX_FFT if mix else P.MIX_NONE,
-                           layout=args.layout, use_graph=args.graph)
+                           fit_target=w.fit_target, mix=kind, layout=args.layout, use_graph=args.graph)
 
     if "mixplan" in legs:
         # the plan's setup (mixing passes with the folded norm and mode-major
@@ -157,6 +157,27 @@ def main():
     torch.cuda.synchronize()
     plain_rate = sum(r["iters"] for r in r0) / (time.perf_counter() - t2)
 
+    # CPRAND-PREMIX (Alg. 5, orthonormal DCT-II) on the same tensor
+    plan2 = P.Plan(Xv, opts(P.MIX_DCT))
+    plan2.run(Xv, [M.clone() for M in init])
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    r2 = [plan2.run(Xv, [M.clone() for M in init]) for _ in range(max(1, args.steps))]
+    torch.cuda.synchronize()
+    pm_s = (time.perf_counter() - t3) / len(r2)
+    pm_pass_ms = [sum(r["mix_ms"][m] for r in r2) / len(r2) for m in range(3)]
+    pm_gbs = [P_el * 8 / (ms * 1e-3) / 1e9 for ms in pm_pass_ms]  # 4 B read + 4 B written per element
+    premix = {"iters_per_step": sum(r["iters"] for r in r2) / len(r2),
+              "iters_per_s": sum(r["iters"] for r in r2) / (pm_s * len(r2)),
+              "ms_per_decomposition": pm_s * 1e3,
+              "loop_iters_per_s": sum(r["iters"] for r in r2) / (sum(r["loop_ms"] for r in r2) * 1e-3),
+              "setup_ms": sum(r["setup_ms"] for r in r2) / len(r2),
+              "final_fit_est": r2[-1]["fit_est"],
+              "dct_pass_ms": pm_pass_ms,
+              "dct_pass_GBps": pm_gbs,
+              "dct_pass_frac_of_hbm": [g / HBM_PEAK_GBS for g in pm_gbs]}
+    del plan2
+
     # gather / sampled-MTTKRP leg: one launch over many samples of X-hat
     Xh, signs, nrm = P.cprand_mix(Xv, w.seed)
     Ah = [P.cprand_mix_factor(M, signs[sum(w.dims[:m]):sum(w.dims[:m + 1])]) for m, M in enumerate(init)]
@@ -202,6 +223,7 @@ def main():
         "mix_pass_ms": mix_ms,
         "plain_cprand_iters_per_s": plain_rate,
         "plain_cprand_iters_per_step": r0[-1]["iters"],
+        "premix_dct": premix,
         "gather_mttkrp": {"samples": Sg, "ms": g_ms, "useful_GBps": gather_gbs,
                           "frac_of_hbm": gather_gbs / HBM_PEAK_GBS},
         "roofline": {"kernel": "mix_pass_pipe", "bound": "hbm", "achieved": mix_achieved,

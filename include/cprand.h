@@ -249,6 +249,41 @@ int cprand_layout_copy(const cprand_tensor *X, int32_t n, const cprand_tensor *Y
                        void *stream);
 
 /* ---------------------------------------------------------------------------
+ * The dense method the paper compares against: CP-ALS (Alg. 1) with the
+ * full MTTKRP, and the exact fit of Section 3.4.  X is a column-major F32 or
+ * F64 tensor; factors are row-major I_m x R of its type.
+ *
+ * cprand_mttkrp_full: W = X_(n) Z^(n) (I_n x R, row-major, FP64), Z^(n) the
+ * Khatri-Rao product of every factor but the n-th in the column order of the
+ * mode-n unfolding (eq. Zn).  Products on MFMA with FP32 accumulation (FP64
+ * for F64 data) over ranges of unfolding columns, the ranges summed in FP64.
+ *
+ * cprand_fit_exact: *fit_out = 1 - ||X - X~|| / ||X|| for X~ = [[lambda;
+ * A^(0), ..., A^(N-1)]], through ||X||^2 - 2 <X, X~> + ||X~||^2 with
+ * <X, X~> from the full MTTKRP of mode 0 and ||X~||^2 = lambda^T (*_m A^(m)T
+ * A^(m)) lambda (FP64).  normX: device ||X||.  lambda: device R doubles.
+ *
+ *   workspace: cprand_full_workspace_size(X, R) bytes.
+ *
+ * cprand_cpals: CP-ALS from A_inout[1..N-1] (A_inout[0] is written before it
+ * is read): per mode, V = Hadamard product of the other factors' Grams, W =
+ * the full MTTKRP, A^(n) = W V^{-1} by the FP64 solve of cprand_solve
+ * (pseudo-inverse when V is not positive definite, CPRAND_W_PINV), columns
+ * normalised into lambda_out.  After every outer iteration the exact fit is
+ * formed from the last mode's MTTKRP (no extra pass over X); the run stops
+ * after max_iters iterations or when the fit changes by at most tol (tol > 0).
+ * fit_history: host, max_iters doubles, or NULL.  Allocates its own scratch;
+ * synchronises the stream once per iteration.  Returns 0, warning bits
+ * (CPRAND_W_PINV, CPRAND_W_MAXIT) or a negative error. */
+size_t cprand_full_workspace_size(const cprand_tensor *X, int32_t R);
+int cprand_mttkrp_full(const cprand_tensor *X, int32_t n, const void *const *A, int32_t R, double *W,
+                       void *workspace, size_t workspace_bytes, void *stream);
+int cprand_fit_exact(const cprand_tensor *X, const double *normX, const void *const *A, const double *lambda,
+                     int32_t R, double *fit_out, void *workspace, size_t workspace_bytes, void *stream);
+int cprand_cpals(const cprand_tensor *X, int32_t R, int32_t max_iters, double tol, void *const *A_inout,
+                 double *lambda_out, double *fit_history, int32_t *iters_out, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Importance proposals for the Khatri-Rao rows of a mode step (a project
  * addition to the paper's uniform sampling of Section 3.2; the leverage
  * definitions are those of Section 2.2).

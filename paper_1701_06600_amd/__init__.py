@@ -236,6 +236,47 @@ def cprand_mix_factor_dct(A, signs, inverse=False, out=None):
     return out
 
 
+def full_workspace(X, R):
+    return torch.empty(max(256, int(_lib.cprand_full_workspace_size(C.byref(X.c()), R))), dtype=torch.uint8,
+                       device=X.data.device)
+
+
+def cprand_mttkrp_full(X, n, A, R, W=None, ws=None):
+    """W = X_(n) Z^(n) (FP64, I_n x R)."""
+    order = len(X.dims)
+    if W is None:
+        W = torch.empty((X.dims[n], R), dtype=torch.float64, device=X.data.device)
+    if ws is None:
+        ws = full_workspace(X, R)
+    arr = _ptr_array([None if m == n else A[m] for m in range(order)], order)
+    _check(_lib.cprand_mttkrp_full(C.byref(X.c()), n, arr, R, _ptr(W), _ptr(ws), ws.numel(), _stream()))
+    return W
+
+
+def cprand_fit_exact(X, normX, A, lam, R, fit_out=None, ws=None):
+    order = len(X.dims)
+    if fit_out is None:
+        fit_out = torch.empty(1, dtype=torch.float64, device=X.data.device)
+    if ws is None:
+        ws = full_workspace(X, R)
+    arr = _ptr_array(A, order)
+    _check(_lib.cprand_fit_exact(C.byref(X.c()), _ptr(normX), arr, _ptr(lam), R, _ptr(fit_out), _ptr(ws), ws.numel(),
+                                 _stream()))
+    return fit_out
+
+
+def cprand_cpals(X, A, R, max_iters, tol=0.0):
+    """Dense CP-ALS from A[1..N-1] (updated in place); returns lambda, the
+    fit history and the status flags."""
+    order = len(X.dims)
+    lam = torch.empty(R, dtype=torch.float64, device=X.data.device)
+    hist = (C.c_double * max_iters)()
+    iters = C.c_int32(0)
+    arr = _ptr_array(A, order)
+    rc = _check(_lib.cprand_cpals(C.byref(X.c()), R, max_iters, tol, arr, _ptr(lam), hist, C.byref(iters), _stream()))
+    return {"lambda": lam, "fit_history": list(hist[:iters.value]), "iters": iters.value, "flags": rc}
+
+
 def cprand_mode_major_strides(dims, n, ld):
     order = len(dims)
     out = (C.c_int64 * order)()

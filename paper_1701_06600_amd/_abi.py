@@ -84,6 +84,13 @@ SIGNATURES = [
                                             C.POINTER(C.c_int64)]),
     ("cprand_layout_copy", C.c_int, [C.POINTER(cprand_tensor), C.c_int32, C.POINTER(cprand_tensor),
                                      C.c_void_p]),
+    ("cprand_full_workspace_size", C.c_size_t, [C.POINTER(cprand_tensor), C.c_int32]),
+    ("cprand_mttkrp_full", C.c_int, [C.POINTER(cprand_tensor), C.c_int32, C.POINTER(C.c_void_p), C.c_int32,
+                                     C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("cprand_fit_exact", C.c_int, [C.POINTER(cprand_tensor), C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p,
+                                   C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("cprand_cpals", C.c_int, [C.POINTER(cprand_tensor), C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_void_p),
+                               C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]),
     ("cprand_mlp_param_count", C.c_int32, []),
     ("cprand_proposal_workspace_size", C.c_size_t, [C.c_int32, C.POINTER(C.c_int64), C.c_int32]),
     ("cprand_proposal", C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.c_int32, C.c_int32, C.POINTER(C.c_void_p),

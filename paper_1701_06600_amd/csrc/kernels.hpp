@@ -105,6 +105,32 @@ hipError_t launch_mix_pass(const FftPlan *fp, bool dbl, const ModeInfo &xi, cons
                            MixExtras *ex, hipStream_t st);
 hipError_t launch_signs(const ModeInfo &mi, uint64_t seed, int8_t *signs, hipStream_t st);
 
+// ---- full MTTKRP, Gram matrices, exact fit (mttkrp_full.hip) ----------------------------
+// Launch shape of the full MTTKRP of mode n of a column-major tensor.
+struct FullPlan {
+    int kind;             // K_F32 or K_F64
+    int32_t In, R, ct;
+    int64_t J, K, Q;      // dims before n, after n, columns of the unfolding
+    bool iv, vec;         // vectors along the fiber (J == 1) / 16-byte vector loads
+    int32_t rows_wg, row_blocks;
+    int64_t qchunk;
+    int32_t chunks;
+    size_t wpart_bytes() const { return (size_t)chunks * R * In * (kind == K_F64 ? 8 : 4); }
+};
+// aligned: X is 16-byte aligned
+FullPlan plan_full(const ModeInfo &mi, int kind, int32_t R, bool aligned);
+// W (row-major I_n x R, FP64) = X_(n) Z^(n); wpart: f.wpart_bytes() of scratch.
+hipError_t launch_mttkrp_full(const FullPlan &f, const ModeInfo &mi, const void *X, const FactorPtrs &A, void *wpart,
+                              double *W, hipStream_t st);
+// G = A^T A (FP64, R x R) of one I x R row-major factor; part: ceil(I/64) R^2 doubles.
+hipError_t launch_gram_full(const void *A, bool dbl, int32_t I, int32_t R, double *part, double *G, hipStream_t st);
+// V = Hadamard product of G[m] (order x R x R), m != skip (skip = -1: all).
+hipError_t launch_gram_hadamard(const double *G, int32_t order, int32_t R, int32_t skip, double *V, hipStream_t st);
+// Exact fit from the mode-n MTTKRP W, the mode-n factor An, lambda and the
+// Hadamard product Gall of every factor's Gram.
+hipError_t launch_fit_exact(const double *W, const void *An, bool dbl, int32_t In, int32_t R, const double *lambda,
+                            const double *Gall, const double *normX, double *fit_out, hipStream_t st);
+
 // ---- real orthogonal mixing (CPRAND-PREMIX) ------------------------------------------
 // One orthonormal DCT-II pass along mode m of a real tensor (dct.hip).  first
 // (m = 0 only): read X (kind xkind, any strides), apply every mode's signs and
