@@ -1,31 +1,36 @@
 """Benchmark: ALS iterations per second of CPRAND-MIX on a 400x400x400 FP32
 tensor (rank 10, column congruence 0.5, 1% noise, S = 10 R ceil(ln R) = 300,
-P-hat = 2^14, stop after 200 iterations, |dF| <= 1e-4 or F >= 1 - 1.2 eta).
+P-hat = 2^14), each decomposition run to the paper's fit target F-hat >=
+1 - 1.2 eta = 0.988 (200 iterations at most).
 
 One step = one whole decomposition on the GPU: ||X||, random signs, the
 mixing pass along every mode, the factor mixes, then the ALS loop (sample,
 sampled Khatri-Rao rows, fiber gather, MTTKRP on MFMA, FP64 solve,
-normalisation, factor remix, sampled fit estimate, stop test).  `value` is
-outer iterations per second of the whole step (mixing included).
+normalisation, factor remix, sampled fit estimate, stop test) and the final
+unmix.  `value` is outer iterations per second of the whole step.
 
 Also reported (not part of `value`):
-  - loop-only iterations per second and the one-time setup time,
-  - plain CPRAND (no mixing) on the same tensor,
+  - the result's exact fit (the library's full-MTTKRP fit check) and factor
+    match score, loop-only rate and one-time setup time,
+  - CPRAND-MIX, plain CPRAND and CPRAND-PREMIX (DCT) over five sampling
+    seeds, to the fit target and with the paper's |dF| <= 1e-4 stop rule
+    (medians and every run),
   - the roofline of the dominant kernel (the mixing pass), from HIP events
     recorded around each pass inside the timed steps,
   - a gather/MTTKRP throughput leg: one cprand_mttkrp_sampled launch over
     many samples of the mixed tensor, timed with HIP events,
+  - the dense comparison: full MTTKRP, exact against sampled fit check,
+    CP-ALS against CPRAND iterations,
   - the CPU oracle (numpy FP64) on a bounded sample of the same work,
   - precision form: 150^4 tensor (R=20, S=1000), BF16 MFMA gathers with one
-    FP32 refinement against the FP32 path, whole decompositions at the paper
-    stop rule, final F-hat of each,
-  - learned proposal: 1000^3 spiky tensor (R=50, congruence 0.9, S=2000);
-    the proposal network is trained on the GPU (100^3 instances, true and
-    initial factors plus ALS iterates), then uniform, CPRAND-MIX, learned and
-    exact-marginal sampling each run one decomposition; final F-hat and the
-    exact fit (evaluated with torch outside the timed runs).
+    FP32 refinement against the FP32 path,
+  - learned proposal: 1000^3 spiky tensor (R=50, congruence 0.9, S=2000),
+    the network trained on the GPU, against uniform, CPRAND-MIX and
+    exact-marginal sampling,
+  - combined form: 60^5 spiky tensor (R=25), learned proposal with BF16
+    products against FP32 CPRAND-MIX.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs main,precision,learned,combined]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs main,dense,precision,learned,combined]
 """
 import argparse
 import json
@@ -58,7 +63,7 @@ def main():
     ap.add_argument("--layout", type=int, default=0, help="0: mode-major copies of X-hat, 1: strided gathers")
     ap.add_argument("--graph", type=int, default=0,
                     help="main leg: 0 direct launches (fit estimate on its own stream), 1 one HIP graph per iteration")
-    ap.add_argument("--legs", default="main,precision,learned,combined")
+    ap.add_argument("--legs", default="main,dense,precision,learned,combined")
     ap.add_argument("--train-instances", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (reference for HBM byte counters)")
@@ -102,9 +107,13 @@ def main():
         print(json.dumps({"mixonly": True, "dims": list(w.dims)}), flush=True)
         return
 
-    def opts(mix, max_iters=w.max_iters):
+    # the main run goes to the paper's fit target F-hat >= 1 - 1.2 eta (or
+    # 200 iterations) with the |dF| <= 1e-4 rule off: that rule stops the
+    # sampled iteration on a plateau far from the noise floor on this tensor
+    # (reported separately below as "paper_stop_rule")
+    def opts(mix, max_iters=w.max_iters, tol=0.0, seed=w.seed):
         kind = P.MIX_FFT if mix is True else (P.MIX_NONE if mix is False else mix)
-        return P.make_opts(R, S, P_hat=w.P_hat, max_iters=max_iters, seed=w.seed, tol=w.tol,
+        return P.make_opts(R, S, P_hat=w.P_hat, max_iters=max_iters, seed=seed, tol=tol,
                            fit_target=w.fit_target, mix=kind, layout=args.layout, use_graph=args.graph)
 
     if "mixplan" in legs:
@@ -118,10 +127,13 @@ def main():
         return
 
     plan = P.Plan(Xv, opts(True))
+    last = {}
 
     def step():
         A = [M.clone() for M in init]
-        return plan.run(Xv, A)
+        r = plan.run(Xv, A)
+        last["A"] = A
+        return r
 
     for _ in range(args.warmup):
         step()
@@ -148,35 +160,44 @@ def main():
     mix_launch_ms = sum(mix_ms) / 3
     mix_achieved = sum(mix_bytes) / 3 / (mix_launch_ms * 1e-3) / 1e9
 
-    # plain CPRAND on the same tensor
-    plan0 = P.Plan(Xv, opts(False))
-    A0 = [M.clone() for M in init]
-    plan0.run(Xv, A0)
-    t2 = time.perf_counter()
-    r0 = [plan0.run(Xv, [M.clone() for M in init]) for _ in range(max(1, args.steps))]
-    torch.cuda.synchronize()
-    plain_rate = sum(r["iters"] for r in r0) / (time.perf_counter() - t2)
+    normX = P.cprand_norm(Xv)
+    truth = prob.factors
 
-    # CPRAND-PREMIX (Alg. 5, orthonormal DCT-II) on the same tensor
-    plan2 = P.Plan(Xv, opts(P.MIX_DCT))
-    plan2.run(Xv, [M.clone() for M in init])
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    r2 = [plan2.run(Xv, [M.clone() for M in init]) for _ in range(max(1, args.steps))]
-    torch.cuda.synchronize()
-    pm_s = (time.perf_counter() - t3) / len(r2)
-    pm_pass_ms = [sum(r["mix_ms"][m] for r in r2) / len(r2) for m in range(3)]
-    pm_gbs = [P_el * 8 / (ms * 1e-3) / 1e9 for ms in pm_pass_ms]  # 4 B read + 4 B written per element
-    premix = {"iters_per_step": sum(r["iters"] for r in r2) / len(r2),
-              "iters_per_s": sum(r["iters"] for r in r2) / (pm_s * len(r2)),
-              "ms_per_decomposition": pm_s * 1e3,
-              "loop_iters_per_s": sum(r["iters"] for r in r2) / (sum(r["loop_ms"] for r in r2) * 1e-3),
-              "setup_ms": sum(r["setup_ms"] for r in r2) / len(r2),
-              "final_fit_est": r2[-1]["fit_est"],
-              "dct_pass_ms": pm_pass_ms,
-              "dct_pass_GBps": pm_gbs,
-              "dct_pass_frac_of_hbm": [g / HBM_PEAK_GBS for g in pm_gbs]}
-    del plan2
+    def evaluate(r, A):
+        F, sc = _evaluate(P, Xv, normX, r["lambda"], A, R, truth)
+        return {"exact_fit": F, "score": sc}
+
+    main_eval = evaluate(runs[-1], last["A"])
+
+    # CPRAND-MIX, plain CPRAND and CPRAND-PREMIX (Alg. 5, orthonormal DCT-II)
+    # over five sampling seeds, to the fit target and with the paper's stop
+    # rule: the iteration count of one sampled run depends on its trajectory
+    seeds = [w.seed + k for k in range(5)]
+    methods = {}
+    dct_pass_ms = None
+    for name, mix in (("mix", P.MIX_FFT), ("plain", P.MIX_NONE), ("premix_dct", P.MIX_DCT)):
+        entry = {}
+        for rule, tol in (("to_fit_target", 0.0), ("paper_stop_rule", w.tol)):
+            recs = []
+            for sd in seeds:
+                pl = P.Plan(Xv, opts(mix, tol=tol, seed=sd))
+                rr, sec, A_c = _timed_median(pl, Xv, init, 3)
+                pl.close()
+                if name == "premix_dct" and dct_pass_ms is None:
+                    dct_pass_ms = rr["mix_ms"][:3]
+                recs.append({"seed": sd, "iters": rr["iters"], "ms_per_decomposition": sec * 1e3,
+                             "iters_per_s": rr["iters"] / sec, "final_fit_est": rr["fit_est"], **evaluate(rr, A_c)})
+            entry[rule] = _medians(recs)
+            entry[rule]["runs"] = recs
+            m_ = entry[rule]
+            print("[bench] %s %s: median %g iters, %.2f ms, fit %.5f, score %.4f"
+                  % (name, rule, m_["iters"], m_["ms_per_decomposition"], m_["exact_fit"], m_["score"]), flush=True)
+        methods[name] = entry
+    # the DCT passes of PREMIX: 4 B read + 4 B written per element each
+    pm_gbs = [P_el * 8 / (ms * 1e-3) / 1e9 for ms in dct_pass_ms]
+    methods["premix_dct"]["dct_pass_ms"] = dct_pass_ms
+    methods["premix_dct"]["dct_pass_GBps"] = pm_gbs
+    methods["premix_dct"]["dct_pass_frac_of_hbm"] = [g / HBM_PEAK_GBS for g in pm_gbs]
 
     # gather / sampled-MTTKRP leg: one launch over many samples of X-hat
     Xh, signs, nrm = P.cprand_mix(Xv, w.seed)
@@ -214,16 +235,16 @@ def main():
         "data": "synthetic",
         "launch": "HIP graph per iteration" if args.graph else "direct launches, fit estimate on a second stream",
         "config": {"workload": "CPRAND-MIX, 400x400x400 FP32, R=10, congruence 0.5, 1% noise, "
-                               "S=300, P-hat=2^14, paper stop rule",
+                               "S=300, P-hat=2^14, run to F-hat >= 1 - 1.2 eta = 0.988 (200 iterations at most)",
                    "layout": "strided X-hat gathers" if args.layout else "mode-major X-hat copies"},
         "iters_per_step": iters / args.steps,
         "final_fit_est": runs[-1]["fit_est"],
+        "exact_fit": main_eval["exact_fit"],
+        "score": main_eval["score"],
         "loop_iters_per_s": iters / (loop_ms * 1e-3),
         "setup_ms": setup_ms,
         "mix_pass_ms": mix_ms,
-        "plain_cprand_iters_per_s": plain_rate,
-        "plain_cprand_iters_per_step": r0[-1]["iters"],
-        "premix_dct": premix,
+        "methods_400cube": methods,
         "gather_mttkrp": {"samples": Sg, "ms": g_ms, "useful_GBps": gather_gbs,
                           "frac_of_hbm": gather_gbs / HBM_PEAK_GBS},
         "roofline": {"kernel": "mix_pass_pipe", "bound": "hbm", "achieved": mix_achieved,
@@ -232,9 +253,11 @@ def main():
                      "copy_GBps": COPY_GBPS},
     }
 
+    if "dense" in legs:
+        out["dense"] = dense_leg(P, torch, Xv, w, init, normX, out)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(X, w, prob, iters / args.steps)
-    del X, Xh, Xv, plan, plan0
+    del X, Xh, Xv, plan
     torch.cuda.empty_cache()
     if "precision" in legs:
         out["precision_form"] = precision_leg(P, synth, torch, dev, max(1, args.steps // 2))
@@ -249,6 +272,124 @@ def main():
                                        synth.WORKLOADS["cprand-1000cube-f32-spiky"])
         out["combined"] = combined_leg(P, synth, torch, dev, theta)
     print(json.dumps(out), flush=True)
+
+
+def _events_ms(torch, fn, reps):
+    """Mean milliseconds of fn() over reps calls, HIP events on the current stream."""
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def dense_leg(P, torch, Xv, w, init, normX, main_out):
+    """The paper's comparison with dense CP-ALS (Section 4.1) on the 400^3
+    tensor, as relative numbers on one GPU: the full MTTKRP of every mode
+    (HBM-bound, one read of X), the exact fit check against the sampled one
+    (P-hat = 2^14), and CP-ALS iterations against CPRAND / CPRAND-MIX
+    iterations (rank 10, S = 300, and the paper's R = 5, S = 90)."""
+    import statistics
+    R, dims = w.R, w.dims
+    P_el = math.prod(dims)
+    lam = torch.full((R,), 0.5, dtype=torch.float64, device="cuda")
+    A = [M.clone() for M in init]
+    ws = P.full_workspace(Xv, R)
+    res = {"workload": "400x400x400 FP32, R=10"}
+    mt = []
+    for n in range(3):
+        W = torch.empty((dims[n], R), dtype=torch.float64, device="cuda")
+        ms = _events_ms(torch, lambda: P.cprand_mttkrp_full(Xv, n, A, R, W=W, ws=ws), 10)
+        gbs = P_el * 4 / (ms * 1e-3) / 1e9
+        mt.append({"mode": n, "ms": ms, "GBps": gbs, "frac_of_hbm": gbs / HBM_PEAK_GBS})
+    res["mttkrp_full"] = mt
+    fo = torch.empty(1, dtype=torch.float64, device="cuda")
+    ex_ms = _events_ms(torch, lambda: P.cprand_fit_exact(Xv, normX, A, lam, R, fit_out=fo, ws=ws), 10)
+    wsf = P.workspace(Xv, R, 1, w.P_hat)
+    est_ms = _events_ms(torch, lambda: P.cprand_fit_est(Xv, normX, A, lam, R, w.P_hat, w.seed, fit_out=fo, ws=wsf), 20)
+    res["fit_check"] = {"exact_ms": ex_ms, "sampled_ms": est_ms, "speedup": ex_ms / est_ms}
+    cp = {}
+    for r_, s_ in ((R, w.S), (5, 90)):
+        Ac = [M[:, :r_].contiguous() for M in init]
+        P.cprand_cpals(Xv, Ac, r_, 2)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            Ac = [M[:, :r_].contiguous() for M in init]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = P.cprand_cpals(Xv, Ac, r_, 10)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) / o["iters"])
+        cp_ms = statistics.median(times) * 1e3
+        entry = {"R": r_, "S": s_, "cpals_ms_per_iter": cp_ms}
+        for name, mix in (("cprand", P.MIX_NONE), ("cprand_mix", P.MIX_FFT)):
+            o = P.make_opts(r_, s_, P_hat=w.P_hat, max_iters=20, seed=w.seed, mix=mix, use_graph=0)
+            pl = P.Plan(Xv, o)
+            Ai = [M[:, :r_].contiguous() for M in init]
+            rr, sec, _ = _timed_median(pl, Xv, Ai, 3)
+            pl.close()
+            per = rr["loop_ms"] / rr["iters"]
+            entry[name + "_ms_per_iter"] = per
+            entry["speedup_" + name] = cp_ms / per
+        cp["R%d_S%d" % (r_, s_)] = entry
+        print("[bench] dense R=%d: CP-ALS %.3f ms/iter, CPRAND %.3f, CPRAND-MIX %.3f"
+              % (r_, cp_ms, entry["cprand_ms_per_iter"], entry["cprand_mix_ms_per_iter"]), flush=True)
+    res["per_iteration"] = cp
+    return res
+
+
+def _score(truth, A):
+    """Factor match score (Section 4.2, eq. score): per pair of true and
+    computed components the product over modes of their signed cosines
+    (lambda ignored), the best one-to-one assignment (Hungarian), averaged
+    over the true components."""
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+    C = None
+    for T, M in zip(truth, A):
+        Tn = T / np.maximum(np.linalg.norm(T, axis=0), 1e-300)
+        Mn = M / np.maximum(np.linalg.norm(M, axis=0), 1e-300)
+        c = Tn.T @ Mn
+        C = c if C is None else C * c
+    rows, cols = linear_sum_assignment(-C)
+    return float(C[rows, cols].sum() / C.shape[0])
+
+
+def _evaluate(P, Xv, normX, lam, A, R, truth):
+    """Exact fit of a result by the library's full-MTTKRP fit check, and its
+    factor match score against the true factors (host, evaluation only)."""
+    import torch
+    F = float(P.cprand_fit_exact(Xv, normX, A, lam, R).item())
+    torch.cuda.synchronize()
+    return F, _score(truth, [M.double().cpu().numpy() for M in A])
+
+
+def _timed_median(plan, Xv, init, reps):
+    """One warm-up decomposition, then `reps` timed ones (each synchronised);
+    returns the last run record, the median wall time and the last factors."""
+    import statistics
+    import torch
+    plan.run(Xv, [M.clone() for M in init])
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        A = [M.clone() for M in init]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = plan.run(Xv, A)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return r, statistics.median(times), A
+
+
+def _medians(recs):
+    import statistics
+    keys = ("iters", "ms_per_decomposition", "iters_per_s", "final_fit_est", "exact_fit", "score")
+    return {k: statistics.median([r[k] for r in recs]) for k in keys}
 
 
 def _timed_runs(plan, Xv, init, reps):
@@ -300,26 +441,6 @@ def precision_leg(P, synth, torch, dev, reps):
     return res
 
 
-def _exact_fit(torch, X, dims, lam, A):
-    """1 - ||X - [[lam; A]]|| / ||X|| for a 3-way column-major FP32 tensor,
-    in FP64 slabs of the last mode (evaluation only)."""
-    I, J, K = dims
-    A = [M.double() for M in A]
-    lam = lam.double()
-    G = (A[0].T @ A[0]) * (A[1].T @ A[1]) * (A[2].T @ A[2])
-    model_sq = float(lam @ G @ lam)
-    inner, xsq = 0.0, 0.0
-    step = max(1, (1 << 27) // (I * J))
-    for k0 in range(0, K, step):
-        k1 = min(K, k0 + step)
-        slab = X[k0 * I * J:k1 * I * J].double().view(k1 - k0, J, I)       # [k, j, i]
-        xsq += float((slab * slab).sum())
-        T = torch.einsum("kji,ir->kjr", slab, A[0])                           # contract mode 0
-        inner += float(torch.einsum("kjr,jr,kr,r->", T, A[1], A[2][k0:k1], lam))
-    res_sq = max(xsq - 2 * inner + model_sq, 0.0)
-    return 1.0 - (res_sq ** 0.5) / (xsq ** 0.5)
-
-
 def learned_leg(P, synth, torch, dev, n_inst):
     """Uniform, CPRAND-MIX, learned and exact-marginal sampling on the
     coherent 1000^3 workload, with the network trained on the GPU first."""
@@ -332,6 +453,7 @@ def learned_leg(P, synth, torch, dev, n_inst):
     X = synth.device_tensor(prob, dev, "f32")
     Xv = P.View(X, w.dims)
     init = [torch.as_tensor(M, dtype=torch.float32, device=dev) for M in prob.init]
+    normX = P.cprand_norm(Xv)
     res = {"workload": "1000x1000x1000 FP32, R=50, congruence 0.9, 10% rows x20, 1% noise, S=2000; each "
                        "method runs until F-hat >= 1 - 1.2 eta = 0.988 (the paper's fit target) or 200 "
                        "iterations (no |dF| rule, so all methods are compared at the same fit)",
@@ -347,9 +469,10 @@ def learned_leg(P, synth, torch, dev, n_inst):
         plan = P.Plan(Xv, opts)
         r, sec = _timed_runs(plan, Xv, init, 1)
         plan.close()
-        fit = _exact_fit(torch, X, w.dims, r["lambda"], r["A"])
+        fit, sc = _evaluate(P, Xv, normX, r["lambda"], r["A"], R, prob.factors)
         res[name] = {"iters": r["iters"], "s_per_decomposition": sec, "iters_per_s": r["iters"] / sec,
-                     "final_fit_est": r["fit_est"], "exact_fit": fit, "reached_target": r["fit_est"] >= w.fit_target,
+                     "final_fit_est": r["fit_est"], "exact_fit": fit, "score": sc,
+                     "reached_target": r["fit_est"] >= w.fit_target,
                      "fell_back": bool(r["flags"] & P.W_FALLBACK)}
         print("[bench] %s: %d iters, %.3f s, F-hat %.5f, fit %.5f" % (name, r["iters"], sec, r["fit_est"], fit),
               flush=True)
@@ -384,33 +507,6 @@ def _train_proposal(P, synth, torch, dev, n_inst, w):
                    "loss_last": hist[-1], "build_s": t_build, "train_s": t_train}
 
 
-def _exact_fit_n(torch, X, dims, lam, A):
-    """1 - ||X - [[lam; A]]|| / ||X|| for a column-major FP32 tensor of any
-    order, in FP64 slabs of the last mode (evaluation only)."""
-    N = len(dims)
-    A = [M.double() for M in A]
-    lam = lam.double()
-    G = torch.ones(lam.shape[0], lam.shape[0], dtype=torch.float64, device=lam.device)
-    for M in A:
-        G = G * (M.T @ M)
-    model_sq = float(lam @ G @ lam)
-    inner, xsq = 0.0, 0.0
-    P_in = math.prod(dims[:-1])
-    step = max(1, (1 << 26) // P_in)
-    for k0 in range(0, dims[-1], step):
-        k1 = min(dims[-1], k0 + step)
-        slab = X[k0 * P_in:k1 * P_in].double()
-        xsq += float((slab * slab).sum())
-        T = slab.view(k1 - k0, P_in // dims[0], dims[0]) @ A[0]        # [k, rest, R], mode 0 contracted
-        rest = P_in // dims[0]
-        for m in range(1, N - 1):
-            T = (T.view(k1 - k0, rest // dims[m], dims[m], -1) * A[m][None, None]).sum(2)
-            rest //= dims[m]
-        inner += float((T.view(k1 - k0, -1) * A[N - 1][k0:k1] * lam).sum())
-    res_sq = max(xsq - 2 * inner + model_sq, 0.0)
-    return 1.0 - (res_sq ** 0.5) / (xsq ** 0.5)
-
-
 def combined_leg(P, synth, torch, dev, theta):
     """The order-5 workload: time to the exact fit that plain FP32
     CPRAND-MIX reaches with the paper's stop rule, for the learned proposal
@@ -426,6 +522,7 @@ def combined_leg(P, synth, torch, dev, theta):
     X = synth.device_tensor(prob, dev, "f32")
     Xv = P.View(X, w.dims)
     init = [torch.as_tensor(M, dtype=torch.float32, device=dev) for M in prob.init]
+    normX = P.cprand_norm(Xv)
     res = {"workload": "60^5 FP32 (BF16 copies for the BF16 form), R=25, congruence 0.7, 10% rows x20, 5% noise, "
                        "S=1000; reference: FP32 CPRAND-MIX to the paper's stop rule (|dF| <= 1e-4, "
                        "F-hat >= 1 - 1.2 eta, 200 iterations); others: time to its exact fit - 1e-3"}
@@ -443,9 +540,10 @@ def combined_leg(P, synth, torch, dev, theta):
         r, sec = _timed_runs(plan, Xv, init, 1)
         plan.close()
         torch.cuda.empty_cache()
-        fit = _exact_fit_n(torch, X, w.dims, r["lambda"], r["A"])
+        fit, sc = _evaluate(P, Xv, normX, r["lambda"], r["A"], w.R, prob.factors)
         return {"iters": r["iters"], "s_per_decomposition": sec, "setup_ms": r["setup_ms"], "layout": layout,
-                "final_fit_est": r["fit_est"], "exact_fit": fit, "fell_back": bool(r["flags"] & P.W_FALLBACK)}
+                "final_fit_est": r["fit_est"], "exact_fit": fit, "score": sc,
+                "fell_back": bool(r["flags"] & P.W_FALLBACK)}
 
     # CPRAND-MIX gathers from mode-major copies of X-hat written by its mixing
     # passes; the unmixed methods gather strided fibers straight from X (at
@@ -480,24 +578,42 @@ def combined_leg(P, synth, torch, dev, theta):
     return res
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(Xdev, w, prob, gpu_iters):
     """The oracle (numpy FP64) on the same tensor: the mixing pass plus a
-    bounded number of ALS iterations; rate = iterations / wall time,
-    directly comparable to `value` when the iteration count matches."""
-    import numpy as np
+    bounded number of ALS iterations; rate = iterations / wall time.  Run
+    with the BLAS thread pool as configured and again with one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import cprand as OC
     from oracle.tensor import from_colmajor
 
     X = from_colmajor(Xdev.double().cpu().numpy(), w.dims)
     k = int(max(1, min(5, round(gpu_iters))))
+    pools = threadpool_info()
+    threads = max([p.get("num_threads", 1) for p in pools] or [1])
     t0 = time.perf_counter()
     lam, A, hist = OC.cprand_mix(X, w.R, w.S, prob.init, w.seed, k, P_hat=w.P_hat)
     dt = time.perf_counter() - t0
-    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        lam, A, hist1 = OC.cprand_mix(X, w.R, w.S, prob.init, w.seed, k, P_hat=w.P_hat)
+        dt1 = time.perf_counter() - t1
     return {"value": len(hist) / dt, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
             "sample": "mixing pass + %d ALS iterations of the same decomposition, numpy FP64, %.1f s"
-                      % (len(hist), dt)}
+                      % (len(hist), dt),
+            "cpu_model": _cpu_model(), "host_logical_cpus": os.cpu_count(),
+            "single_thread": {"value": len(hist1) / dt1, "seconds": dt1}}
 
 
 if __name__ == "__main__":
