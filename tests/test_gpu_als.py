@@ -42,6 +42,25 @@ def test_cprand_50cube_f64_tracks_oracle(use_graph):
 
 
 @pytest.mark.parametrize("use_graph", [0, 1])
+@pytest.mark.parametrize("patience", [2, 4])
+def test_patience_rule_stops_like_the_oracle(use_graph, patience):
+    """Stop when the best F-hat has not improved for `patience` iterations
+    (the rule of the paper's real-data runs, Section 4.3 and 4.4): the GPU
+    stops at the oracle's iteration, with the same F-hat history (FP64)."""
+    w = synth.WORKLOADS["cprand-50cube-f64"]
+    p = synth.problem_for(w)
+    X = synth.dense_tensor(p)
+    out, A = _run_gpu(X, p.init, w.R, w.S, w.seed, torch.float64, max_iters=200, patience=patience,
+                      use_graph=use_graph)
+    lam_r, A_r, hist_r = OC.cprand(X, w.R, w.S, p.init, w.seed, 200, patience=patience)
+    assert len(hist_r) < 200
+    assert out["iters"] == len(hist_r)
+    assert np.max(np.abs(np.array(out["fit_history"]) - np.array(hist_r))) < 1e-8
+    best = int(np.argmax(hist_r))
+    assert len(hist_r) - 1 - best == patience   # the stop fired exactly `patience` iterations after the best
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
 def test_cprand_f32_stop_rules_and_fit(use_graph):
     """Stops before max_iters, so the iteration launched past the stop is
     undone from the saved state (graph: saved by the fit kernel; direct
