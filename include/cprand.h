@@ -189,6 +189,44 @@ int cprand_fit_est(const cprand_tensor *X, const double *normX, const void *cons
                    const double *lambda, int32_t R, int32_t P_hat, uint64_t seed,
                    double *fit_out, void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Importance-weighted fit estimate (a project addition to Section 3.4 for
+ * unmixed tensors whose energy sits in few slices, where few uniformly
+ * drawn entries see the residual).  Entries come from a defensive mixture:
+ * with probability beta from the product over modes of the proposal tables
+ * cdf[m] (as cprand_sample reads them), else uniformly.  Entry p uses
+ * Philox4x64-10 with key (seed, 6) and counter (p, 1, 0, b); word j of the
+ * sequence (block j / 4, word j % 4) serves as: j = 0, the component (the
+ * product when (u >> 11) < floor(beta 2^53)); j = k + 1, the row of mode k
+ * (the table search of cprand_sample for the product, floor(u I_k / 2^64)
+ * otherwise).  The weight of entry i is
+ *   w = 1 / (beta P prod_k (q_k(i_k) / Q_k) + (1 - beta)),
+ * in FP64 with the operations in that order (no fused multiply-add), so
+ * P mean(w e^2) estimates ||X - X~||^2 without bias and w <= 1 / (1 - beta);
+ * beta = 0 gives the paper's estimate on a uniform set.
+ *
+ * cprand_energy_proposals: the tables of the slice energies of X, s_m(i) =
+ * sum of x^2 over the entries with index i in mode m, mixed with uniform by
+ * alpha and quantised like cprand_proposal: cdf_out[m] (device, I_m + 1
+ * uint64).  The energies are summed in 64-bit fixed point (x^2 scaled by
+ * 2^62 / (||X||^2 (1 + 1e-6))), so the tables are the same at every call;
+ * energy_out (device, sum I_m doubles, mode 0 first, or NULL) receives
+ * them.  normX: device ||X||.  workspace: 8 sum I_m bytes.
+ * cprand_fit_set_weighted: the rows (idx, device P_hat x order int32) and
+ * weights (w, device P_hat doubles) of the set.
+ * cprand_fit_est_weighted: *fit_out = 1 - sqrt(P mean(w |x - model|^2)) /
+ * normX over that set.  workspace: cprand_fit_weighted_workspace_size(order,
+ * P_hat) bytes. */
+size_t cprand_fit_weighted_workspace_size(int32_t order, int32_t P_hat);
+int cprand_energy_proposals(const cprand_tensor *X, const double *normX, double alpha, uint64_t *const *cdf_out,
+                            double *energy_out, void *workspace, size_t workspace_bytes, void *stream);
+int cprand_fit_set_weighted(int32_t order, const int64_t *dims, int32_t P_hat, uint64_t seed,
+                            const uint64_t *const *cdf, double beta, int32_t *idx, double *w, void *stream);
+int cprand_fit_est_weighted(const cprand_tensor *X, const double *normX, const void *const *A,
+                            const double *lambda, int32_t R, int32_t P_hat, uint64_t seed,
+                            const uint64_t *const *cdf, double beta, double *fit_out, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
 /* ||X|| (Frobenius, FP64 sums over all elements) into device *normX_out. */
 int cprand_norm(const cprand_tensor *X, double *normX_out, void *workspace,
                 size_t workspace_bytes, void *stream);
@@ -292,7 +330,8 @@ int cprand_cpals(const cprand_tensor *X, int32_t R, int32_t max_iters, double to
  * gets a distribution over its rows: CPRAND_PROPOSAL_MARGINAL uses the exact
  * marginal of Khatri-Rao leverage, L(i) = a_i^T (G_K^{-1} * prod_{k in K,
  * k != m} G_k) a_i (G_k = A^(k)T A^(k), G_K their Hadamard product, * =
- * Hadamard); CPRAND_PROPOSAL_LEARNED uses softmax over rows of a 4-64-64-1
+ * Hadamard); CPRAND_PROPOSAL_LEVERAGE uses the row's leverage in its own
+ * factor, a_i^T G_m^{-1} a_i; CPRAND_PROPOSAL_LEARNED uses softmax over rows of a 4-64-64-1
  * ReLU network (params, cprand_mlp_param_count() floats) applied to the row
  * features (log f1, log f2, log f3, f4): f1 = I|a_i|^2/|A|_F^2, f2 = (I/R)
  * a_i^T G_m^{-1} a_i, f3 = (I/R) sum_r a_ir^2/(G_m)_rr, f4 = mean |cosine|
@@ -304,6 +343,9 @@ int cprand_cpals(const cprand_tensor *X, int32_t R, int32_t max_iters, double to
  */
 #define CPRAND_PROPOSAL_MARGINAL 3
 #define CPRAND_PROPOSAL_MIXTURE 4  /* reported in proposal_history: fallback, alpha = 0.5 */
+#define CPRAND_PROPOSAL_LEVERAGE 5 /* each factor's rows by their leverage in that factor alone,
+                                      a_i^T G_m^{-1} a_i (the product of factor leverages over the
+                                      other modes, a non-learned reference proposal) */
 
 int32_t cprand_mlp_param_count(void);
 size_t cprand_proposal_workspace_size(int32_t order, const int64_t *dims, int32_t R);
@@ -364,8 +406,8 @@ typedef struct cprand_opts {
     int32_t patience;     /* stop when the best F has not improved for this many iterations (0 = off) */
     int32_t mix;          /* CPRAND_MIX_* */
     int32_t precision;    /* CPRAND_PREC_* */
-    int32_t proposal;     /* CPRAND_PROPOSAL_*: UNIFORM; TABLE (fixed caller tables); LEARNED or
-                             MARGINAL (recomputed from the current factors at every mode step,
+    int32_t proposal;     /* CPRAND_PROPOSAL_*: UNIFORM; TABLE (fixed caller tables); LEARNED,
+                             MARGINAL or LEVERAGE (recomputed from the current factors at every mode step,
                              FP32 tensors without mixing; falls back to a half-uniform mixture and
                              then to uniform sampling when the fit estimate drops by more than
                              three of its standard deviations below the best, twice in a row) */
@@ -377,6 +419,9 @@ typedef struct cprand_opts {
     int32_t refine_every; /* PREC_BF16_REFINE: 1 = refine every solve; 0 = BF16 solves until the stop
                              rule first holds (or one iteration before max_iters), then refined
                              solves until it holds again */
+    double fit_beta;      /* 0 = the uniform fit set of Section 3.4; in (0, 1): the importance-weighted
+                             fit set of cprand_fit_est_weighted with this beta (not with MIX_FFT) */
+    double fit_alpha;     /* with fit_beta > 0: uniform share of the slice-energy proposals, (0, 1] */
 } cprand_opts;
 
 typedef struct cprand_report {

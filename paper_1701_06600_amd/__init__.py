@@ -18,7 +18,7 @@ import torch
 from . import _abi
 from ._abi import (BF16, C64, C128, EHIP, EINVAL, ENAN, ENOMEM, EUNSUPPORTED, F32, F64, MIX_DCT, MIX_FFT,
                    MIX_NONE, OK, PREC_BF16, PREC_BF16_REFINE, PREC_NATIVE, PROPOSAL_LEARNED,
-                   PROPOSAL_MARGINAL, PROPOSAL_MIXTURE, PROPOSAL_TABLE, PROPOSAL_UNIFORM, W_FALLBACK,
+                   PROPOSAL_LEVERAGE, PROPOSAL_MARGINAL, PROPOSAL_MIXTURE, PROPOSAL_TABLE, PROPOSAL_UNIFORM, W_FALLBACK,
                    W_MAXIT, W_PINV)
 
 _lib = _abi.load()
@@ -167,6 +167,42 @@ def cprand_fit_est(X, normX, A, lam, R, P_hat, seed, fit_out=None, ws=None):
     arr = _ptr_array(A, order)
     _check(_lib.cprand_fit_est(C.byref(X.c()), _ptr(normX), arr, _ptr(lam), R, P_hat, C.c_uint64(seed),
                                _ptr(fit_out), _ptr(ws), ws.numel(), _stream()))
+    return fit_out
+
+
+def cprand_energy_proposals(X, normX, alpha=0.1, cdf_out=None, energy_out=None):
+    """Slice-energy proposal tables of every mode (and the slice energies)."""
+    dev = X.data.device
+    order = len(X.dims)
+    if cdf_out is None:
+        cdf_out = [torch.empty(I + 1, dtype=torch.uint64, device=dev) for I in X.dims]
+    if energy_out is None:
+        energy_out = torch.empty(sum(X.dims), dtype=torch.float64, device=dev)
+    ws = torch.empty(8 * sum(X.dims), dtype=torch.uint8, device=dev)
+    _check(_lib.cprand_energy_proposals(C.byref(X.c()), _ptr(normX), alpha, _ptr_array(cdf_out, order),
+                                        _ptr(energy_out), _ptr(ws), ws.numel(), _stream()))
+    return cdf_out, energy_out
+
+
+def cprand_fit_set_weighted(dims, P_hat, seed, cdf, beta, device="cuda"):
+    order = len(dims)
+    idx = torch.empty((P_hat, order), dtype=torch.int32, device=device)
+    w = torch.empty(P_hat, dtype=torch.float64, device=device)
+    _check(_lib.cprand_fit_set_weighted(order, (C.c_int64 * order)(*dims), P_hat, C.c_uint64(seed),
+                                        _ptr_array(cdf, order), beta, _ptr(idx), _ptr(w), _stream()))
+    return idx, w
+
+
+def cprand_fit_est_weighted(X, normX, A, lam, R, P_hat, seed, cdf, beta, fit_out=None, ws=None):
+    order = len(X.dims)
+    if fit_out is None:
+        fit_out = torch.empty(1, dtype=torch.float64, device=X.data.device)
+    if ws is None:
+        ws = torch.empty(int(_lib.cprand_fit_weighted_workspace_size(order, P_hat)), dtype=torch.uint8,
+                         device=X.data.device)
+    _check(_lib.cprand_fit_est_weighted(C.byref(X.c()), _ptr(normX), _ptr_array(A, order), _ptr(lam), R, P_hat,
+                                        C.c_uint64(seed), _ptr_array(cdf, order), beta, _ptr(fit_out), _ptr(ws),
+                                        ws.numel(), _stream()))
     return fit_out
 
 
@@ -370,7 +406,7 @@ def cprand_mlp_train(params, X, t, group_off, epochs, lr=1e-3):
 
 def make_opts(R, S, P_hat=2 ** 14, max_iters=50, seed=0, tol=0.0, fit_target=2.0, patience=0,
               mix=MIX_NONE, precision=PREC_NATIVE, proposal=PROPOSAL_UNIFORM, layout=0, use_graph=1,
-              alpha=0.1, proposal_cdf=None, mlp_params=None, refine_every=0):
+              alpha=0.1, proposal_cdf=None, mlp_params=None, refine_every=0, fit_beta=0.0, fit_alpha=0.1):
     o = _abi.cprand_opts()
     o.R, o.S, o.P_hat, o.max_iters = R, S, P_hat, max_iters
     o.seed = seed
@@ -378,6 +414,7 @@ def make_opts(R, S, P_hat=2 ** 14, max_iters=50, seed=0, tol=0.0, fit_target=2.0
     o.mix, o.precision, o.proposal, o.layout, o.use_graph = mix, precision, proposal, layout, use_graph
     o.alpha = alpha
     o.refine_every = refine_every
+    o.fit_beta, o.fit_alpha = fit_beta, fit_alpha
     keep = []
     if proposal_cdf is not None:
         arr = (C.c_void_p * len(proposal_cdf))(*[c.data_ptr() for c in proposal_cdf])

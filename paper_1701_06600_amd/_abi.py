@@ -22,6 +22,7 @@ NOALLOC_SCRATCH_BYTES = 32 << 20
 MIX_NONE, MIX_FFT, MIX_DCT = 0, 1, 2
 PREC_NATIVE, PREC_BF16_REFINE, PREC_BF16 = 0, 1, 2
 PROPOSAL_UNIFORM, PROPOSAL_TABLE, PROPOSAL_LEARNED, PROPOSAL_MARGINAL, PROPOSAL_MIXTURE = 0, 1, 2, 3, 4
+PROPOSAL_LEVERAGE = 5
 
 
 class cprand_tensor(C.Structure):
@@ -36,7 +37,8 @@ class cprand_opts(C.Structure):
                 ("patience", C.c_int32), ("mix", C.c_int32), ("precision", C.c_int32),
                 ("proposal", C.c_int32), ("layout", C.c_int32), ("use_graph", C.c_int32),
                 ("alpha", C.c_double), ("proposal_cdf", C.POINTER(C.c_void_p)),
-                ("mlp_params", C.c_void_p), ("refine_every", C.c_int32)]
+                ("mlp_params", C.c_void_p), ("refine_every", C.c_int32), ("fit_beta", C.c_double),
+                ("fit_alpha", C.c_double)]
 
 
 class cprand_report(C.Structure):
@@ -71,6 +73,14 @@ SIGNATURES = [
     ("cprand_fit_est", C.c_int, [C.POINTER(cprand_tensor), C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p,
                                  C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p, C.c_size_t,
                                  C.c_void_p]),
+    ("cprand_fit_weighted_workspace_size", C.c_size_t, [C.c_int32, C.c_int32]),
+    ("cprand_energy_proposals", C.c_int, [C.POINTER(cprand_tensor), C.c_void_p, C.c_double, C.POINTER(C.c_void_p),
+                                          C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("cprand_fit_set_weighted", C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.c_int32, C.c_uint64,
+                                          C.POINTER(C.c_void_p), C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("cprand_fit_est_weighted", C.c_int, [C.POINTER(cprand_tensor), C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p,
+                                          C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_void_p), C.c_double,
+                                          C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("cprand_norm", C.c_int, [C.POINTER(cprand_tensor), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("cprand_mix", C.c_int, [C.POINTER(cprand_tensor), C.c_uint64, C.POINTER(cprand_tensor), C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),

@@ -103,6 +103,11 @@ struct cprand_plan {
     size_t snapbytes = 0;
     int32_t *frow = nullptr; // the fixed fit set: rows [P_hat][N] and tensor values [P_hat][2]
     double *fx = nullptr;
+    // importance-weighted fit set (fit_beta > 0): entry weights, slice-energy
+    // proposal tables and their fixed-point bins
+    double *fw = nullptr;
+    uint64_t *fcdf[CPRAND_MAX_ORDER] = {};
+    unsigned long long *fbins = nullptr;
     void *ysum = nullptr;
     uint64_t *t_dev = nullptr;
     unsigned *counter = nullptr;
@@ -296,6 +301,7 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
         } else if (p->adaptive) {
             // proposals for the factors of this step from their current values
             const bool learned = p->o.proposal == CPRAND_PROPOSAL_LEARNED;
+            const bool marginal = p->o.proposal == CPRAND_PROPOSAL_MARGINAL;
             ModeInfo pm{};
             pm.order = N;
             pm.n = n;
@@ -305,9 +311,9 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
                 pm.strides[m] = 1;
                 fp.p[m] = (m == n) ? nullptr : p->fac[m];
             }
-            e = launch_mode_stats(fp, pm, R, p->pstats, p->pgpart, learned ? nullptr : p->pH, st);
+            e = launch_mode_stats(fp, pm, R, p->pstats, p->pgpart, marginal ? p->pH : nullptr, st);
             if (e == hipSuccess)
-                e = launch_row_scores(fp, pm, R, p->pstats, learned ? nullptr : p->pH, p->o.mlp_params, learned,
+                e = launch_row_scores(fp, pm, R, p->pstats, marginal ? p->pH : nullptr, p->o.mlp_params, learned,
                                       p->pscore, nullptr, nullptr, nullptr, st);
             uint64_t *cd[CPRAND_MAX_ORDER] = {};
             for (int m = 0; m < N; ++m) cd[m] = (m == n) ? nullptr : p->pcdf[m];
@@ -450,6 +456,7 @@ hipError_t enqueue_iteration(cprand_plan *p, const void *xdata, bool contig_x[CP
     FitArgs fa = fit_args(p, xdata);
     fa.frow = p->frow;
     fa.fx = p->fx;
+    fa.fw = p->fw;
     if (ic) {
         // iteration t's state is in snapshot buffer t mod 2: estimate from it on the fit stream
         for (int m = 0; m < N; ++m) fa.A.p[m] = snap_segment(p, sb, m);
@@ -507,12 +514,17 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
     if (o.precision != CPRAND_PREC_NATIVE && xk != K_F32)
         return set_error(CPRAND_EINVAL, "the BF16 form reads an F32 tensor");
     if (o.precision != CPRAND_PREC_NATIVE && cmix) return set_error(CPRAND_EUNSUPPORTED, "BF16 with FFT mixing");
+    if (!(o.fit_beta >= 0.0 && o.fit_beta < 1.0)) return set_error(CPRAND_EINVAL, "fit_beta outside [0, 1)");
+    if (o.fit_beta > 0.0 && !(o.fit_alpha > 0.0 && o.fit_alpha <= 1.0))
+        return set_error(CPRAND_EINVAL, "fit_alpha outside (0, 1]");
+    if (o.fit_beta > 0.0 && cmix) return set_error(CPRAND_EUNSUPPORTED, "a weighted fit set with FFT mixing");
     if (o.proposal == CPRAND_PROPOSAL_TABLE) {
         if (!o.proposal_cdf) return set_error(CPRAND_EINVAL, "PROPOSAL_TABLE needs proposal_cdf");
         for (int m = 0; m < X->order; ++m)
             if (!o.proposal_cdf[m]) return set_error(CPRAND_EINVAL, "proposal_cdf[%d] is NULL", m);
         if (cmix) return set_error(CPRAND_EUNSUPPORTED, "importance sampling with FFT mixing");
-    } else if (o.proposal == CPRAND_PROPOSAL_LEARNED || o.proposal == CPRAND_PROPOSAL_MARGINAL) {
+    } else if (o.proposal == CPRAND_PROPOSAL_LEARNED || o.proposal == CPRAND_PROPOSAL_MARGINAL ||
+               o.proposal == CPRAND_PROPOSAL_LEVERAGE) {
         if (o.proposal == CPRAND_PROPOSAL_LEARNED && !o.mlp_params)
             return set_error(CPRAND_EINVAL, "PROPOSAL_LEARNED needs mlp_params");
         if (xk != K_F32) return set_error(CPRAND_EUNSUPPORTED, "adaptive proposals read FP32 factors");
@@ -662,8 +674,18 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
         if (e == hipSuccess) e = dalloc(p, &p->snapbuf[1], p->snapbytes);
     }
     if (e == hipSuccess) e = dalloc(p, (void **)&p->fx, (size_t)o.P_hat * 16);
+    if (e == hipSuccess && o.fit_beta > 0.0) {
+        e = dalloc(p, (void **)&p->fw, (size_t)o.P_hat * 8);
+        int64_t tot = 0;
+        for (int m = 0; m < N && e == hipSuccess; ++m) {
+            e = dalloc(p, (void **)&p->fcdf[m], (size_t)(p->dims[m] + 1) * 8);
+            tot += p->dims[m];
+        }
+        if (e == hipSuccess) e = dalloc(p, (void **)&p->fbins, (size_t)tot * 8);
+    }
     if (e == hipSuccess && p->mix) e = dalloc(p, &p->ysum, (size_t)maxdim * 2 * R * tsz);
-    p->adaptive = o.proposal == CPRAND_PROPOSAL_LEARNED || o.proposal == CPRAND_PROPOSAL_MARGINAL;
+    p->adaptive = o.proposal == CPRAND_PROPOSAL_LEARNED || o.proposal == CPRAND_PROPOSAL_MARGINAL ||
+                  o.proposal == CPRAND_PROPOSAL_LEVERAGE;
     {
         // the samples depend only on (seed, t, n) unless the proposal adapts:
         // draw them all at setup for direct-launch loops
@@ -859,7 +881,17 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
                               p->o.proposal == CPRAND_PROPOSAL_TABLE ? &cdf : nullptr, p->pre_idx, p->pre_w, st);
     }
     // the fixed fit set: rows and tensor values drawn once per run
-    if (e == hipSuccess) e = launch_fit_set(fit_args(p, xit), p->frow, p->fx, st);
+    if (e == hipSuccess && p->fw) {
+        // the weighted fit set: slice-energy tables of the iterated tensor, then the draw
+        CdfPtrs c{};
+        for (int m = 0; m < N; ++m) c.p[m] = p->fcdf[m];
+        e = launch_energy_tables(xit_i, xit, p->xkind, p->normX, p->fbins, p->o.fit_alpha, c, nullptr, st);
+        if (e == hipSuccess)
+            e = launch_fit_set_weighted(xit_i, xit, p->xkind, p->o.P_hat, p->o.seed, c, p->o.fit_beta, p->frow, p->fx,
+                                        p->fw, st);
+    } else if (e == hipSuccess) {
+        e = launch_fit_set(fit_args(p, xit), p->frow, p->fx, st);
+    }
     if (e == hipSuccess) e = hipEventRecord(p->ev[1], st);
     if (e != hipSuccess) return hip_fail(e, "setup");
 

@@ -344,6 +344,114 @@ int cprand_fit_est(const cprand_tensor *X, const double *normX, const void *cons
     return e == hipSuccess ? CPRAND_OK : hip_fail(e, "cprand_fit_est");
 }
 
+size_t cprand_fit_weighted_workspace_size(int32_t order, int32_t P_hat) {
+    if (order < 2 || order > CPRAND_MAX_ORDER || P_hat < 1) return 0;
+    return align256((size_t)fit_partials(P_hat) * 8) + align256((size_t)P_hat * order * 4) +
+           align256((size_t)P_hat * 16) + align256((size_t)P_hat * 8);
+}
+
+int cprand_energy_proposals(const cprand_tensor *X, const double *normX, double alpha, uint64_t *const *cdf_out,
+                            double *energy_out, void *workspace, size_t workspace_bytes, void *stream) {
+    g_last_error.clear();
+    int rc = check_tensor(X, "X");
+    if (rc) return rc;
+    const int kind = kind_of(X->dtype);
+    if (kind != K_F64 && kind != K_F32 && kind != K_BF16) return set_error(CPRAND_EINVAL, "X must be real");
+    if (!normX || !cdf_out) return set_error(CPRAND_EINVAL, "normX and cdf_out must be non-NULL");
+    if (!(alpha > 0.0 && alpha <= 1.0)) return set_error(CPRAND_EINVAL, "alpha outside (0, 1]");
+    CdfPtrs c{};
+    size_t bins = 0;
+    for (int m = 0; m < X->order; ++m) {
+        if (!cdf_out[m]) return set_error(CPRAND_EINVAL, "cdf_out[%d] is NULL", m);
+        c.p[m] = cdf_out[m];
+        bins += (size_t)X->dims[m];
+    }
+    if (!workspace || workspace_bytes < bins * 8)
+        return set_error(CPRAND_EINVAL, "workspace of %zu bytes needed", bins * 8);
+    hipError_t e = launch_energy_tables(mode_info(X, 0), X->data, kind, normX, (unsigned long long *)workspace, alpha,
+                                        c, energy_out, (hipStream_t)stream);
+    return e == hipSuccess ? CPRAND_OK : hip_fail(e, "cprand_energy_proposals");
+}
+
+static int check_weighted_set(int32_t order, const int64_t *dims, int32_t P_hat, const uint64_t *const *cdf,
+                              double beta, CdfPtrs *c) {
+    if (order < 2 || order > CPRAND_MAX_ORDER || !dims) return set_error(CPRAND_EINVAL, "bad order or dims");
+    if (P_hat < 1) return set_error(CPRAND_EINVAL, "P_hat = %d < 1", P_hat);
+    if (!(beta >= 0.0 && beta < 1.0)) return set_error(CPRAND_EINVAL, "beta outside [0, 1)");
+    if (!cdf) return set_error(CPRAND_EINVAL, "cdf is NULL");
+    for (int m = 0; m < order; ++m) {
+        if (dims[m] < 1 || dims[m] > (int64_t)INT32_MAX) return set_error(CPRAND_EINVAL, "dims[%d] invalid", m);
+        if (!cdf[m]) return set_error(CPRAND_EINVAL, "cdf[%d] is NULL", m);
+        c->p[m] = cdf[m];
+    }
+    return CPRAND_OK;
+}
+
+int cprand_fit_set_weighted(int32_t order, const int64_t *dims, int32_t P_hat, uint64_t seed,
+                            const uint64_t *const *cdf, double beta, int32_t *idx, double *w, void *stream) {
+    g_last_error.clear();
+    CdfPtrs c{};
+    int rc = check_weighted_set(order, dims, P_hat, cdf, beta, &c);
+    if (rc) return rc;
+    if (!idx || !w) return set_error(CPRAND_EINVAL, "idx and w must be non-NULL");
+    ModeInfo mi{};
+    mi.order = order;
+    for (int m = 0; m < order; ++m) {
+        mi.dims[m] = dims[m];
+        mi.strides[m] = 1;
+    }
+    hipError_t e = launch_fit_set_weighted(mi, nullptr, K_F32, P_hat, seed, c, beta, idx, nullptr, w,
+                                           (hipStream_t)stream);
+    return e == hipSuccess ? CPRAND_OK : hip_fail(e, "cprand_fit_set_weighted");
+}
+
+int cprand_fit_est_weighted(const cprand_tensor *X, const double *normX, const void *const *A, const double *lambda,
+                            int32_t R, int32_t P_hat, uint64_t seed, const uint64_t *const *cdf, double beta,
+                            double *fit_out, void *workspace, size_t workspace_bytes, void *stream) {
+    g_last_error.clear();
+    int rc = check_tensor(X, "X");
+    if (rc) return rc;
+    const int kind = kind_of(X->dtype);
+    if (kind != K_F64 && kind != K_F32 && kind != K_BF16) return set_error(CPRAND_EINVAL, "X must be real");
+    if (R < 1 || R > CPRAND_MAX_RANK) return set_error(CPRAND_EINVAL, "R = %d outside [1, %d]", R, CPRAND_MAX_RANK);
+    CdfPtrs c{};
+    rc = check_weighted_set(X->order, X->dims, P_hat, cdf, beta, &c);
+    if (rc) return rc;
+    if (!normX || !A || !lambda || !fit_out) return set_error(CPRAND_EINVAL, "NULL pointer argument");
+    for (int m = 0; m < X->order; ++m)
+        if (!A[m]) return set_error(CPRAND_EINVAL, "A[%d] is NULL", m);
+    const size_t need = cprand_fit_weighted_workspace_size(X->order, P_hat);
+    if (!workspace || workspace_bytes < need) return set_error(CPRAND_EINVAL, "workspace of %zu bytes needed", need);
+    char *ws = (char *)workspace;
+    double *part = (double *)ws;
+    int32_t *frow = (int32_t *)(ws + align256((size_t)fit_partials(P_hat) * 8));
+    double *fx = (double *)((char *)frow + align256((size_t)P_hat * X->order * 4));
+    double *fw = (double *)((char *)fx + align256((size_t)P_hat * 16));
+    hipStream_t st = (hipStream_t)stream;
+    const ModeInfo mi = mode_info(X, 0);
+    hipError_t e = launch_fit_set_weighted(mi, X->data, kind, P_hat, seed, c, beta, frow, fx, fw, st);
+    FitArgs fa{};
+    fa.mi = mi;
+    fa.X = X->data;
+    fa.kind = kind;
+    for (int m = 0; m < X->order; ++m) fa.A.p[m] = A[m];
+    fa.fdouble = kind == K_F64;
+    fa.cplx = false;
+    fa.lambda = lambda;
+    fa.R = R;
+    fa.P_hat = P_hat;
+    fa.seed = seed;
+    fa.part = part;
+    fa.frow = frow;
+    fa.fx = fx;
+    fa.fw = fw;
+    int32_t nb = 0;
+    if (e == hipSuccess) e = launch_fit_partial(fa, &nb, st);
+    if (e == hipSuccess)
+        e = launch_fit_final(part, nb, P_hat, (double)numel(X), normX, fit_out, nullptr, nullptr, st);
+    return e == hipSuccess ? CPRAND_OK : hip_fail(e, "cprand_fit_est_weighted");
+}
+
 int cprand_norm(const cprand_tensor *X, double *normX_out, void *workspace, size_t workspace_bytes, void *stream) {
     g_last_error.clear();
     int rc = check_tensor(X, "X");

@@ -83,8 +83,8 @@ int cprand_proposal(int32_t order, const int64_t *dims, int32_t n, int32_t R, co
     g_last_error.clear();
     int rc = check_dims(order, dims, n, R);
     if (rc) return rc;
-    if (kind != CPRAND_PROPOSAL_LEARNED && kind != CPRAND_PROPOSAL_MARGINAL)
-        return set_error(CPRAND_EINVAL, "kind must be PROPOSAL_LEARNED or PROPOSAL_MARGINAL");
+    if (kind != CPRAND_PROPOSAL_LEARNED && kind != CPRAND_PROPOSAL_MARGINAL && kind != CPRAND_PROPOSAL_LEVERAGE)
+        return set_error(CPRAND_EINVAL, "kind must be PROPOSAL_LEARNED, PROPOSAL_MARGINAL or PROPOSAL_LEVERAGE");
     if (kind == CPRAND_PROPOSAL_LEARNED && !params) return set_error(CPRAND_EINVAL, "params is NULL");
     if (!(alpha >= 0.0 && alpha <= 1.0)) return set_error(CPRAND_EINVAL, "alpha outside [0, 1]");
     if (!A || !cdf_out) return set_error(CPRAND_EINVAL, "A and cdf_out must be non-NULL");

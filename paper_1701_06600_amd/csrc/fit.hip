@@ -137,6 +137,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_partial_kernel(FitArgs a) {
     __shared__ int s_last;
     __shared__ int32_t s_row[kFitSamplesPerBlock * kMaxOrder];
     __shared__ double s_x[kFitSamplesPerBlock * 2];
+    __shared__ double s_w[kFitSamplesPerBlock];
     const int tid = threadIdx.x;
     const int N = a.mi.order;
     const int64_t p0 = (int64_t)blockIdx.x * kFitSamplesPerBlock;
@@ -172,6 +173,8 @@ __global__ __launch_bounds__(kFitThreads) void fit_partial_kernel(FitArgs a) {
             const int e = tid + u * kFitThreads;
             xv[u] = e < 2 * ne ? a.fx[2 * p0 + e] : 0.0;
         }
+        if (a.fw)
+            for (int e = tid; e < ne; e += kFitThreads) s_w[e] = a.fw[p0 + e];
 #pragma unroll
         for (int u = 0; u < kRowLoads; ++u) s_row[tid + u * kFitThreads] = rv[u];
 #pragma unroll
@@ -226,7 +229,8 @@ __global__ __launch_bounds__(kFitThreads) void fit_partial_kernel(FitArgs a) {
         const int q = grp + kFitGroups * j;
         if (lane == 0 && q < ne) {
             const double dr = s_x[2 * q] - mr[j], di = s_x[2 * q + 1] - mi[j];
-            e2 += dr * dr + di * di;
+            const double sq = dr * dr + di * di;
+            e2 += (a.frow && a.fw) ? s_w[q] * sq : sq;
         }
     }
     const double s = block_sum<kFitThreads>(e2, sh);

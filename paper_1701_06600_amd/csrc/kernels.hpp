@@ -105,6 +105,19 @@ hipError_t launch_mix_pass(const FftPlan *fp, bool dbl, const ModeInfo &xi, cons
                            MixExtras *ex, hipStream_t st);
 hipError_t launch_signs(const ModeInfo &mi, uint64_t seed, int8_t *signs, hipStream_t st);
 
+// ---- importance-weighted fit set (fitset.hip) ------------------------------------------
+// Slice-energy proposal tables of every mode (cdf.p[m]: I_m + 1 uint64) from
+// one pass over X; bins: sum I_m uint64 of scratch; energy_out (sum I_m
+// doubles, mode 0 first) receives the slice energies when non-NULL.
+hipError_t launch_energy_tables(const ModeInfo &mi, const void *X, int kind, const double *normX,
+                                unsigned long long *bins, double alpha, const CdfPtrs &cdf, double *energy_out,
+                                hipStream_t st);
+// The P_hat entries of the weighted fit set: rows [P_hat][order], values
+// [P_hat][2] (fx may be NULL) and weights [P_hat].
+hipError_t launch_fit_set_weighted(const ModeInfo &mi, const void *X, int kind, int32_t P_hat, uint64_t seed,
+                                   const CdfPtrs &cdf, double beta, int32_t *frow, double *fx, double *fw,
+                                   hipStream_t st);
+
 // ---- full MTTKRP, Gram matrices, exact fit (mttkrp_full.hip) ----------------------------
 // Launch shape of the full MTTKRP of mode n of a column-major tensor.
 struct FullPlan {
@@ -236,6 +249,7 @@ struct FitArgs {
     // from Philox and loaded from X.
     const int32_t *frow;
     const double *fx;
+    const double *fw;     // with frow: per-entry weights of a weighted fit set, or NULL (all 1)
     // Optional copy of the iteration's state (iteration *t_dev, before the
     // advance), spread over all blocks.
     SnapArgs snap;

@@ -198,7 +198,8 @@ __device__ inline float mlp_part(const float *P, const float *W2p, const float x
 }
 
 // Row scores for every mode m != n: mode == LEARNED: the network's logit;
-// mode == MARGINAL: log of the exact marginal.  Also (optionally) writes the
+// mode == MARGINAL: log of the exact marginal; neither (no Hinv): log of the
+// row's leverage in its own factor, a_i^T G_m^{-1} a_i.  Also (optionally) writes the
 // feature rows and the exact targets L/R for training.  One workgroup of
 // four waves per kScoreRows rows: G^{-1}, the marginal matrix H_m = Hinv *
 // prod_{k in K\{m}} G_k (Hadamard products), the rows (transposed) and the
@@ -354,8 +355,8 @@ __global__ __launch_bounds__(kScoreThreads) void row_scores_kernel(RowArgs a) {
         if (a.learned) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) sX[tid * 4 + k] = x[k];
-        } else if (a.score[m]) {
-            a.score[m][i] = logf((float)fmax(mg, 1e-30));
+        } else if (a.score[m]) {  // the exact marginal, or (no marginals) the factor's own leverage
+            a.score[m][i] = logf((float)fmax(marg ? mg : lev, 1e-30));
         }
         if (a.feat) {
             float *f = a.feat + (a.row_off[m] + i) * 4;

@@ -181,7 +181,8 @@ def test_binding_constants_match_header_defines():
     names = ["MAX_ORDER", "MAX_RANK", "OK", "W_PINV", "W_MAXIT", "W_FALLBACK", "EINVAL", "ENAN", "EHIP",
              "ENOMEM", "EUNSUPPORTED", "F64", "F32", "BF16", "C64", "C128", "MIX_NONE", "MIX_FFT", "MIX_DCT",
              "PREC_NATIVE", "PREC_BF16_REFINE", "PREC_BF16", "PROPOSAL_UNIFORM", "PROPOSAL_TABLE",
-             "PROPOSAL_LEARNED", "PROPOSAL_MARGINAL", "PROPOSAL_MIXTURE", "NOALLOC_SCRATCH_BYTES"]
+             "PROPOSAL_LEARNED", "PROPOSAL_MARGINAL", "PROPOSAL_MIXTURE", "PROPOSAL_LEVERAGE",
+             "NOALLOC_SCRATCH_BYTES"]
     for n in names:
         assert n in d, "CPRAND_%s is not #defined in the header" % n
         assert getattr(_abi, n) == d[n], (n, getattr(_abi, n), d[n])

@@ -40,6 +40,22 @@ def test_marginal_proposal_matches_exact_leverage(dims, R, n):
         close(_probs(cdf[m]), want, 2e-4)
 
 
+@pytest.mark.parametrize("dims,R,n", [((80, 60, 70), 5, 0), ((40, 33, 25, 18), 12, 2)])
+def test_leverage_proposal_matches_factor_leverage(dims, R, n):
+    """PROPOSAL_LEVERAGE: each other factor's rows by their leverage in that
+    factor alone (Section 2.2's leverage of a single matrix), mixed with
+    uniform; the product over the modes is the proposal of a sample."""
+    A = _factors(4, dims, R)
+    alpha = 0.1
+    cdf = P.cprand_proposal(dims, n, R, factors_dev(A), P.PROPOSAL_LEVERAGE, alpha=alpha)
+    for m in range(len(dims)):
+        if m == n:
+            continue
+        lev = OL.leverage_scores(A[m])
+        want = (1 - alpha) * lev / lev.sum() + alpha / dims[m]
+        close(_probs(cdf[m]), want, 2e-4)
+
+
 def test_learned_proposal_matches_oracle_network():
     dims, R, n = (70, 60, 50), 6, 1
     A = _factors(2, dims, R)
