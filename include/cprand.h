@@ -241,7 +241,7 @@ int cprand_norm(const cprand_tensor *X, double *normX_out, void *workspace,
  * (scaled by 1/sqrt(I_m)).  X is real (F32 or F64, any strides); Xhat is a
  * caller-allocated complex tensor (C64 for F32 input, C128 for F64) with
  * column-major strides.  ||X|| is written to device *normX_out.  Every I_m
- * must factor into 2, 3, 5 and 7.
+ * must factor into 2, 3, 5 and 7 and be at most 10240 (C64) or 5120 (C128).
  */
 int cprand_mix(const cprand_tensor *X, uint64_t seed, const cprand_tensor *Xhat,
                int8_t *signs, double *normX_out, void *workspace, size_t workspace_bytes,
@@ -264,8 +264,8 @@ int cprand_mix_factor(int32_t I, int32_t R, const void *A, int32_t dtype,
  * F32 or F64 with any strides; Xhat is a caller-allocated column-major
  * tensor of the same dtype and dims that does not overlap X.  signs and
  * normX_out as for cprand_mix (||Xhat|| = ||X||).  Every I_m must factor
- * into 2, 3, 5 and 7 and be at most 4096 (F32) or 2048 (F64); otherwise
- * CPRAND_EUNSUPPORTED.  workspace: 32768 bytes.
+ * into 2, 3, 5 and 7 and be at most 3413 (F32) or 1706 (F64), the lengths
+ * whose transform tile fits in LDS; otherwise CPRAND_EUNSUPPORTED.  workspace: 32768 bytes.
  *
  * cprand_mix_factor_dct: A-hat = F D A for one I x R row-major real factor
  * (dtype F32 or F64; A and out do not overlap); with inverse != 0, A =

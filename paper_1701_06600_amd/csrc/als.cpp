@@ -550,6 +550,17 @@ int cprand_plan_create(const cprand_tensor *X, const cprand_opts *opts, cprand_p
         p->P *= X->dims[m];
     }
     const int N = p->N, R = o.R;
+    if (p->premix) {
+        // the DCT pass keeps one tile of two real fibers, the complex FFT tiles
+        // and the post-rotation table in LDS
+        const int64_t dct_max = p->dbl ? 1706 : 3413;
+        for (int m = 0; m < N; ++m)
+            if (p->dims[m] > dct_max && p->dims[m] != 400 && p->dims[m] != 150 && p->dims[m] != 60) {
+                delete p;
+                return set_error(CPRAND_EUNSUPPORTED, "mode %d length %lld is too long for the DCT pass", m,
+                                 (long long)X->dims[m]);
+            }
+    }
     if (p->mix || p->premix) {
         for (int m = 0; m < N; ++m) {
             hipError_t fe;

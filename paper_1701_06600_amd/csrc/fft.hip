@@ -378,15 +378,21 @@ __global__ __launch_bounds__(256) void mix_pass_rt(FftPlan fp, const Tin *X, cx<
                                                    int tc, int first, ModeInfo xi, int m, const int8_t *signs) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int L = (int)fp.L;
-    const int ldt = tc + 1;
+    // tc = 0: a long fiber, one per workgroup, unpadded, twiddles read from
+    // global memory (L2) so the two tiles alone fill the LDS
+    const bool glong = tc == 0;
+    if (glong) tc = 1;
+    const int ldt = glong ? 1 : tc + 1;
     cx<T> *b0 = (cx<T> *)lds, *b1 = b0 + L * ldt;
-    cx<T> *tw = b1 + L * ldt;
+    cx<T> *twl = b1 + L * ldt;
+    const cx<T> *tw = glong ? (const cx<T> *)fp.tw : twl;
     __shared__ int64_t cbase[16];
     __shared__ double csign[16];
     const int64_t ncols = J * K;
     const int64_t q0 = (int64_t)blockIdx.x * tc;
     const int nc = (int)min((int64_t)tc, ncols - q0);
-    for (int e = threadIdx.x; e < L; e += blockDim.x) tw[e] = ((const cx<T> *)fp.tw)[e];
+    if (!glong)
+        for (int e = threadIdx.x; e < L; e += blockDim.x) twl[e] = ((const cx<T> *)fp.tw)[e];
     int moff = 0;
     for (int mm = 0; mm < m; ++mm) moff += (int)xi.dims[mm];
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
@@ -449,8 +455,12 @@ __global__ __launch_bounds__(256) void mix_pass_rt(FftPlan fp, const Tin *X, cx<
     }
 }
 
-// Columns per tile of the generic path: two tiles + twiddles within ~64 KB.
+// Columns per tile of the generic path: two tiles + twiddles within ~64 KB;
+// 0 (one unpadded fiber, twiddles from global memory) when even one padded
+// column and its twiddles would not fit in the 160 KB of LDS.
+constexpr size_t kLdsMax = 160 * 1024;
 static int tile_cols(int64_t L, int esz) {
+    if ((2 * (size_t)L * 2 + (size_t)L) * (size_t)esz > kLdsMax) return 0;
     int64_t tc = (int64_t)(65536 / esz - L) / (2 * L) - 1;
     if (tc > 16) tc = 16;
     if (tc < 1) tc = 1;
@@ -461,9 +471,12 @@ static int tile_cols(int64_t L, int esz) {
 // the R columns (one workgroup per launch would run the FFT stages serially).
 static int tile_cols_for(int64_t L, int esz, int R) {
     const int per = (R + 7) / 8;
-    return std::max(1, std::min(tile_cols(L, esz), per));
+    const int tc = tile_cols(L, esz);
+    return tc == 0 ? 0 : std::max(1, std::min(tc, per));
 }
-static size_t tile_lds(int64_t L, int tc, size_t esz) { return (2 * (size_t)L * (tc + 1) + (size_t)L) * esz; }
+static size_t tile_lds(int64_t L, int tc, size_t esz) {
+    return tc == 0 ? 2 * (size_t)L * esz : (2 * (size_t)L * (tc + 1) + (size_t)L) * esz;
+}
 
 // ---------------------------------------------------------------------------
 // Factor mix (A-hat = F D A), inverse factor mix (A = Re(D F^* A-hat)) and
@@ -474,10 +487,14 @@ __global__ __launch_bounds__(256) void factor_mix_kernel(FftPlan fp, const T *in
                                                          int tc, int inverse) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int L = (int)fp.L;
-    const int ldt = tc + 1;
+    const bool glong = tc == 0;  // long fibers: see mix_pass_rt
+    if (glong) tc = 1;
+    const int ldt = glong ? 1 : tc + 1;
     cx<T> *b0 = (cx<T> *)lds, *b1 = b0 + L * ldt;
-    cx<T> *tw = b1 + L * ldt;
-    for (int e = threadIdx.x; e < L; e += blockDim.x) tw[e] = ((const cx<T> *)fp.tw)[e];
+    cx<T> *twl = b1 + L * ldt;
+    const cx<T> *tw = glong ? (const cx<T> *)fp.tw : twl;
+    if (!glong)
+        for (int e = threadIdx.x; e < L; e += blockDim.x) twl[e] = ((const cx<T> *)fp.tw)[e];
     const int r0 = blockIdx.x * tc;
     const int nc = min(tc, R - r0);
     for (int e = threadIdx.x; e < L * tc; e += blockDim.x) {
@@ -516,10 +533,14 @@ __global__ __launch_bounds__(256) void unmix_kernel(FftPlan fp, const T *ypart, 
                                                     T *W, int rowmajor, int tc) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int L = (int)fp.L;
-    const int ldt = tc + 1;
+    const bool glong = tc == 0;  // long fibers: see mix_pass_rt
+    if (glong) tc = 1;
+    const int ldt = glong ? 1 : tc + 1;
     cx<T> *b0 = (cx<T> *)lds, *b1 = b0 + L * ldt;
-    cx<T> *tw = b1 + L * ldt;
-    for (int e = threadIdx.x; e < L; e += blockDim.x) tw[e] = ((const cx<T> *)fp.tw)[e];
+    cx<T> *twl = b1 + L * ldt;
+    const cx<T> *tw = glong ? (const cx<T> *)fp.tw : twl;
+    if (!glong)
+        for (int e = threadIdx.x; e < L; e += blockDim.x) twl[e] = ((const cx<T> *)fp.tw)[e];
     const int r0 = blockIdx.x * tc;
     const int nc = min(tc, R - r0);
     const size_t cstride = (size_t)2 * R * L;
@@ -581,7 +602,8 @@ FftPlan *fft_plan_get(int64_t L, bool dbl, hipError_t *err) {
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     // the generic tile (two buffers of L x 2 plus twiddles) must fit in LDS
-    if (L < 1 || L > (dbl ? 2048 : 4096)) {
+    // the long-fiber layout holds two unpadded tiles of L in LDS
+    if (L < 1 || (size_t)L * (dbl ? 16 : 8) * 2 > kLdsMax) {
         *err = hipErrorInvalidValue;
         return nullptr;
     }
@@ -742,7 +764,7 @@ hipError_t launch_mix_pass(const FftPlan *fp, bool dbl, const ModeInfo &xi, cons
     }
     const size_t esz = dbl ? 16 : 8;
     const int tc = tile_cols(fp->L, (int)esz);
-    const int64_t nb = ceil_div(J * K, tc);
+    const int64_t nb = ceil_div(J * K, std::max(tc, 1));
     const size_t lds = tile_lds(fp->L, tc, esz);
     if (dbl) {
         hipLaunchKernelGGL((mix_pass_rt<double, double>), dim3((unsigned)nb), dim3(256), lds, st, *fp,
@@ -761,7 +783,7 @@ hipError_t launch_factor_mix(const FftPlan *fp, bool dbl, int32_t I, int32_t R, 
                              void *out, bool inverse, hipStream_t st) {
     const size_t esz = dbl ? 16 : 8;
     const int tc = tile_cols_for(fp->L, (int)esz, (int)R);
-    const int nb = (int)ceil_div(R, tc);
+    const int nb = (int)ceil_div(R, std::max(tc, 1));
     const size_t lds = tile_lds(fp->L, tc, esz);
     if (dbl)
         hipLaunchKernelGGL(factor_mix_kernel<double>, dim3(nb), dim3(256), lds, st, *fp, (const double *)in, sign,
@@ -776,7 +798,7 @@ hipError_t launch_unmix(const FftPlan *fp, bool dbl, int32_t In, int32_t R, int3
                         const int8_t *sign, void *W, bool w_rowmajor, hipStream_t st) {
     const size_t esz = dbl ? 16 : 8;
     const int tc = tile_cols_for(fp->L, (int)esz, (int)R);
-    const int nb = (int)ceil_div(R, tc);
+    const int nb = (int)ceil_div(R, std::max(tc, 1));
     const size_t lds = tile_lds(fp->L, tc, esz);
     if (dbl)
         hipLaunchKernelGGL(unmix_kernel<double>, dim3(nb), dim3(256), lds, st, *fp, (const double *)ypart, chunks, R,

@@ -251,16 +251,26 @@ __global__ __launch_bounds__(kWaves * 64) void full_mttkrp_kernel(FullArgs a) {
     }
 }
 
-// W[i][r] = sum over chunks of wpart[chunk][r][i], FP64, chunks in order.
+// W[i][r] = sum over chunks of wpart[chunk][r][i] in FP64: a workgroup takes
+// 64 consecutive entries of the [R][In] order, its four waves the chunks
+// c = wave, wave + 4, ... (coalesced 64-entry rows), and the four wave sums
+// are added in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void full_reduce_kernel(const T *wpart, int32_t chunks, int32_t In, int32_t R,
                                                           double *W) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)In * R) return;
-    const int r = (int)(e / In), i = (int)(e - (int64_t)r * In);
+    __shared__ double sh[4][64];
+    const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t n = (int64_t)In * R;
+    const int64_t e = (int64_t)blockIdx.x * 64 + l;
     double s = 0.0;
-    for (int c = 0; c < chunks; ++c) s += (double)wpart[((size_t)c * R + r) * In + i];
-    W[(int64_t)i * R + r] = s;
+    if (e < n)
+        for (int c = g; c < chunks; c += 4) s += (double)wpart[(size_t)c * n + e];
+    sh[g][l] = s;
+    __syncthreads();
+    if (g == 0 && e < n) {
+        const int r = (int)(e / In), i = (int)(e - (int64_t)r * In);
+        W[(int64_t)i * R + r] = (sh[0][l] + sh[1][l]) + (sh[2][l] + sh[3][l]);
+    }
 }
 
 // Gram partials of one factor over a block of kGramRows rows: part[blk][r][q]
@@ -409,7 +419,7 @@ hipError_t launch_mttkrp_full(const FullPlan &f, const ModeInfo &mi, const void 
     a.wpart = wpart;
     hipError_t e = f.kind == K_F64 ? launch_full_ct<double>(f, a, st) : launch_full_ct<float>(f, a, st);
     if (e != hipSuccess) return e;
-    const unsigned nb = (unsigned)ceil_div((int64_t)f.In * f.R, 256);
+    const unsigned nb = (unsigned)ceil_div((int64_t)f.In * f.R, 64);
     if (f.kind == K_F64)
         hipLaunchKernelGGL(full_reduce_kernel<double>, dim3(nb), dim3(256), 0, st, (const double *)wpart, f.chunks,
                            f.In, f.R, W);
