@@ -63,7 +63,7 @@ def main():
     ap.add_argument("--layout", type=int, default=0, help="0: mode-major copies of X-hat, 1: strided gathers")
     ap.add_argument("--graph", type=int, default=0,
                     help="main leg: 0 direct launches (fit estimate on its own stream), 1 one HIP graph per iteration")
-    ap.add_argument("--legs", default="main,dense,precision,learned,combined,standins")
+    ap.add_argument("--legs", default="main,dense,precision,learned,combined,standins,gather")
     ap.add_argument("--train-instances", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (reference for HBM byte counters)")
@@ -90,9 +90,15 @@ def main():
     import paper_1701_06600_amd as P
     import synth
 
+    dev = torch.device("cuda:0")
+    if "main" not in legs and "mixonly" not in legs and "mixplan" not in legs:
+        # only the named side legs (profiling runs); no headline line
+        out = {"legs": sorted(legs)}
+        _extra_legs(P, synth, torch, dev, args, legs, out)
+        print(json.dumps(out), flush=True)
+        return
     w = synth.WORKLOADS["cprand-400cube-f32"]
     R, S = w.R, w.S
-    dev = torch.device("cuda:0")
     prob = synth.problem_for(w)
     print("[bench] generating %s on the GPU" % (w.name,), flush=True)
     X = synth.device_tensor(prob, dev, "f32")
@@ -259,6 +265,12 @@ def main():
         out["cpu_baseline"] = cpu_baseline(X, w, prob, iters / args.steps)
     del X, Xh, Xv, plan
     torch.cuda.empty_cache()
+    _extra_legs(P, synth, torch, dev, args, legs, out)
+    print(json.dumps(out), flush=True)
+
+
+def _extra_legs(P, synth, torch, dev, args, legs, out):
+    """The legs beside the main one, each on its own workload."""
     if "precision" in legs:
         out["precision_form"] = precision_leg(P, synth, torch, dev, max(1, args.steps // 2))
         torch.cuda.empty_cache()
@@ -274,7 +286,9 @@ def main():
         torch.cuda.empty_cache()
     if "standins" in legs:
         out["standins"] = standin_leg(P, synth, torch, dev)
-    print(json.dumps(out), flush=True)
+        torch.cuda.empty_cache()
+    if "gather" in legs:
+        out["gather_throughput"] = gather_leg(P, synth, torch, dev)
 
 
 def _events_ms(torch, fn, reps):
@@ -585,6 +599,49 @@ def combined_leg(P, synth, torch, dev, theta, nseeds=3):
     res["equal_fit"] = bool(a["equal_fit"])
     res["speedup_vs_mix_fp32"] = a["speedup_vs_mix_fp32"]
     del X, Xv
+    torch.cuda.empty_cache()
+    return res
+
+
+def gather_leg(P, synth, torch, dev, reps=10):
+    """Throughput of the sampled MTTKRP at the shape of a mode step but with
+    enough uniformly drawn samples (many independent draws' worth, one
+    launch) that each call moves about 1 GB of fibers: FP32 fibers of 1000
+    (the 1000^3 tensor, mode 0, contiguous) and complex64 fibers of 400 (the
+    mixed 400^3 tensor, mode 0), rank 10.  Useful bytes = S I_n b_X per call;
+    the 1000^3 tensor has 10^6 fibers per mode, so few of the 256,000 draws
+    repeat a fiber (the cache cannot serve them)."""
+    R = 10
+    res = {}
+    cases = []
+    w4 = synth.WORKLOADS["cprand-1000cube-f32-spiky"]
+    prob4 = synth.problem_for(w4)
+    print("[bench] generating %s for the gather leg" % w4.name, flush=True)
+    X4 = synth.device_tensor(prob4, dev, "f32")
+    cases.append(("f32_1000cube_mode0", P.View(X4, w4.dims), w4.dims, 0, 256000, 4,
+                  [torch.as_tensor(M[:, :R], dtype=torch.float32, device=dev).contiguous() for M in prob4.init], None))
+    w2 = synth.WORKLOADS["cprand-400cube-f32"]
+    prob2 = synth.problem_for(w2)
+    X2 = synth.device_tensor(prob2, dev, "f32")
+    Xh, signs, _ = P.cprand_mix(P.View(X2, w2.dims), w2.seed)
+    del X2
+    init2 = [torch.as_tensor(M, dtype=torch.float32, device=dev) for M in prob2.init]
+    Ah = [P.cprand_mix_factor(M, signs[sum(w2.dims[:m]):sum(w2.dims[:m + 1])]) for m, M in enumerate(init2)]
+    cases.append(("c64_400cube_mixed_mode0", Xh, w2.dims, 0, 320000, 8, Ah, signs[:w2.dims[0]]))
+    for name, Xv, dims, n, S, bx, A, sg in cases:
+        idx, _ = P.cprand_sample(dims, n, S, 1701066100, 0)
+        ws = P.workspace(Xv, R, S)
+        Wg = torch.empty((dims[n], R), dtype=torch.float32, device=dev)
+        Vg = torch.empty((R, R), dtype=torch.float64, device=dev)
+        ms = _events_ms(torch, lambda: P.cprand_mttkrp_sampled(Xv, n, A, R, S, idx, unmix_signs=sg, W=Wg, V=Vg,
+                                                               ws=ws), reps)
+        useful = S * dims[n] * bx
+        gbs = useful / (ms * 1e-3) / 1e9
+        res[name] = {"samples": S, "fiber_len": dims[n], "bytes_per_call": useful, "ms_per_call": ms,
+                     "useful_GBps": gbs, "frac_of_hbm": gbs / HBM_PEAK_GBS}
+        print("[bench] gather %s: %.3f ms per call, %.0f GB/s useful (%.2f of HBM)"
+              % (name, ms, gbs, gbs / HBM_PEAK_GBS), flush=True)
+    del X4, Xh
     torch.cuda.empty_cache()
     return res
 
