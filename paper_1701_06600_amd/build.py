@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcprand.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["sample.hip", "mttkrp.hip", "mttkrp_bf16.hip", "mttkrp_full.hip", "solve.hip", "step.hip", "fit.hip", "fitset.hip", "fft.hip", "dct.hip",
+SOURCES = ["sample.hip", "mttkrp.hip", "mttkrp_stream.hip", "mttkrp_bf16.hip", "mttkrp_full.hip", "solve.hip", "step.hip", "fit.hip", "fitset.hip", "fft.hip", "dct.hip",
            "layout.hip", "proposal.hip", "noalloc.hip", "api.cpp", "api_proposal.cpp", "cpals.cpp", "als.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

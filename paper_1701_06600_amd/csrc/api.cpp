@@ -109,10 +109,13 @@ WsLayout ws_layout(const cprand_tensor *X, int32_t R, int32_t S, int32_t P_hat) 
     const int kind = kind_of(X->dtype);
     size_t wpart = 0, vpart = 0;
     for (int n = 0; n < X->order; ++n) {
-        GatherPlan gp = plan_gather(kind, R, S, X->dims[n], true);
-        const size_t tsz = (kind == K_F64 || kind == K_C128) ? 8 : 4;
-        wpart = std::max(wpart, gp.wpart_elems() * tsz);
-        vpart = std::max(vpart, gp.vpart_elems() * 8);
+        // the vector-load (streaming for long sample sets) and the strided plans
+        for (bool contig : {true, false}) {
+            GatherPlan gp = plan_gather(kind, R, S, X->dims[n], contig, 0, X->order);
+            const size_t tsz = (kind == K_F64 || kind == K_C128) ? 8 : 4;
+            wpart = std::max(wpart, gp.wpart_elems() * tsz);
+            vpart = std::max(vpart, gp.vpart_elems() * 8);
+        }
     }
     int64_t maxdim = 1;
     for (int n = 0; n < X->order; ++n) maxdim = std::max(maxdim, X->dims[n]);
@@ -151,7 +154,7 @@ int check_mttkrp_args(const cprand_tensor *X, int32_t n, const void *const *A, i
 void mttkrp_scratch_bytes(const cprand_tensor *X, int32_t n, int32_t R, int32_t S, size_t *wpart, size_t *vpart) {
     const int kind = kind_of(X->dtype);
     const bool contig = fibers_vectorizable(X->data, kind, X->strides, X->order, n);
-    GatherPlan gp = plan_gather(kind, R, S, X->dims[n], contig);
+    GatherPlan gp = plan_gather(kind, R, S, X->dims[n], contig, 0, X->order);
     const size_t tsz = (kind == K_F64 || kind == K_C128) ? 8 : 4;
     *wpart = gp.wpart_elems() * tsz;
     *vpart = gp.vpart_elems() * 8;
@@ -163,7 +166,7 @@ int mttkrp_sampled_run(const cprand_tensor *X, int32_t n, const void *const *A, 
     const int kind = kind_of(X->dtype);
     const bool cplx = kind == K_C64 || kind == K_C128;
     const bool contig = fibers_vectorizable(X->data, kind, X->strides, X->order, n);
-    GatherPlan gp = plan_gather(kind, R, S, X->dims[n], contig);
+    GatherPlan gp = plan_gather(kind, R, S, X->dims[n], contig, 0, X->order);
     GatherArgs ga{};
     ga.mi = mode_info(X, n);
     ga.X = X->data;

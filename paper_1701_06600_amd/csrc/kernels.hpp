@@ -33,6 +33,8 @@ struct GatherPlan {
     int32_t waves;      // waves per workgroup
     int32_t row_blocks; // gridDim.x
     bool contig;        // vector loads along the fiber
+    bool stream;        // streaming form: chunks = sample splits of per_split samples
+    int32_t per_split;
     size_t lds_bytes;
     size_t wpart_elems() const { return (size_t)chunks * (size_t)ncols * (size_t)In; }
     size_t vpart_elems() const { return (size_t)chunks * (size_t)R * (size_t)R; }
@@ -42,7 +44,9 @@ struct GatherPlan {
 // and every stride other than mode n allow 16-byte vector loads along fibers.
 // max_chunks > 0 caps the number of sample chunks (partial products) for
 // consumers that sum them inside one workgroup.
-GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks = 0);
+// order: the tensor's order (sizes the per-sample index slots in LDS).
+GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks = 0,
+                       int order = kMaxOrder);
 
 struct GatherArgs {
     ModeInfo mi;

@@ -15,106 +15,9 @@
 // are a fixed permutation that the store undoes.  Partial products of every
 // chunk go to a workspace and are summed by the consumer in a fixed order
 // (deterministic results).
-#include "kernels.hpp"
+#include "mttkrp_device.hpp"
 
 namespace cprand {
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct AccT;
-template <>
-struct AccT<float> {
-    typedef v4f type;
-};
-template <>
-struct AccT<double> {
-    typedef v4d type;
-};
-
-__device__ inline v4f mfma16(float a, float b, v4f c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ inline v4d mfma16(double a, double b, v4d c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-template <typename T, bool CPLX>
-struct Geo {
-    static constexpr int NV = 16 / (int)sizeof(T);          // reals per 16-byte vector
-    static constexpr int VE = CPLX ? NV / 2 : NV;          // fiber rows per lane per step
-    static constexpr int RPW = 16 * VE;                    // rows per wave per step
-};
-
-constexpr int kUnroll = 8;  // k-steps (of 4 samples) whose fiber loads are in flight together
-constexpr int kWholeFiberS = 4096;  // sample sets from this size on use whole-fiber workgroups
-
-// LDS row stride (in T) for the B operand: >= 16*CT and, for float, an odd
-// multiple of 16 words so that two B rows read by one half-wave hit
-// disjoint banks.
-__host__ __device__ constexpr int ldb_for(int ct, int tsize) {
-    return tsize == 4 ? (ct % 2 ? 16 * ct : 16 * ct + 16) : 16 * ct + 2;
-}
-
-struct KArgs {
-    ModeInfo mi;
-    const void *X;
-    FactorPtrs A;
-    const int32_t *idx;
-    const double *w;
-    CdfPtrs cdf;
-    int use_cdf;
-    uint64_t seed, t;
-    const uint64_t *t_dev;
-    void *wpart;
-    double *vpart;
-    int32_t R, S, In, ncols, kc, rows_wg;
-};
-
-// Fiber values of one MFMA batch: lane (li, lk) takes sample ks + 4u + lk
-// (u < kUnroll) and rows row0 .. row0 + VE - 1 of its mode-n fiber.
-template <typename T, bool CPLX, bool CONTIG>
-__device__ __forceinline__ void load_fibers(T (&v)[kUnroll][16 / sizeof(T)], const T *xp, const int64_t *s_base,
-                                            int ns, int ks, int row0, int lk, int In, int64_t sn) {
-    typedef Geo<T, CPLX> G;
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        const int sl = ks + 4 * u + lk;
-#pragma unroll
-        for (int e = 0; e < G::NV; ++e) v[u][e] = (T)0;
-        if (sl < ns && row0 < In) {
-            const int64_t b = s_base[sl];
-            if (CONTIG && row0 + G::VE <= In) {
-                const T *src = xp + (b + row0) * (CPLX ? 2 : 1);
-                if (sizeof(T) == 4) {
-                    const float4 q = *(const float4 *)src;
-                    v[u][0] = q.x;
-                    v[u][1] = q.y;
-                    v[u][2] = q.z;
-                    v[u][3] = q.w;
-                } else {
-                    const double2 q = *(const double2 *)src;
-                    v[u][0] = q.x;
-                    v[u][1] = q.y;
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < G::VE; ++c) {
-                    if (row0 + c < In) {
-                        const int64_t o = b + (int64_t)(row0 + c) * sn;
-                        if (CPLX) {
-                            v[u][2 * c] = xp[2 * o];
-                            v[u][2 * c + 1] = xp[2 * o + 1];
-                        } else {
-                            v[u][c] = xp[o];
-                        }
-                    }
-                }
-            }
-        }
-    }
-}
 
 template <typename T, bool CPLX, int CT, bool CONTIG, bool WEIGHTED>
 __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
@@ -142,35 +45,7 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
 
     // ---- (1) indices, weights and fiber offsets
     const uint64_t tt = a.t_dev ? *a.t_dev : a.t;
-    for (int sl = tid; sl < KC; sl += nthr) {
-        int64_t row[kMaxOrder];
-        double wv = 1.0;
-        int64_t base = 0;
-        // mode loops unrolled to kMaxOrder: row[] stays in registers
-        if (sl < ns) {
-            const int64_t s = s0 + sl;
-            if (a.idx) {
-#pragma unroll
-                for (int m = 0; m < kMaxOrder; ++m)
-                    if (m < N) row[m] = (m == n) ? 0 : a.idx[s * N + m];
-                if (a.w) wv = a.w[s];
-            } else {
-                wv = draw_sample(a.mi, a.seed, tt, s, a.cdf, a.use_cdf != 0, row);
-            }
-#pragma unroll
-            for (int m = 0; m < kMaxOrder; ++m)
-                if (m < N && m != n) base += row[m] * a.mi.strides[m];
-        } else {
-#pragma unroll
-            for (int m = 0; m < kMaxOrder; ++m) row[m] = 0;
-            wv = 0.0;
-        }
-#pragma unroll
-        for (int m = 0; m < kMaxOrder; ++m)
-            if (m < N) s_idx[sl * N + m] = (m == n) ? 0 : (int32_t)row[m];
-        s_base[sl] = base;
-        s_w[sl] = wv;
-    }
+    chunk_indices(a, tt, s0, ns, KC, s_base, s_w, s_idx, tid);
     // zero the B operand tiles (padding columns and samples stay zero)
     {
         const int words = (int)(((size_t)KC * LDB * sizeof(T) * ((CPLX || WEIGHTED) ? 2 : 1)) / 4);
@@ -190,70 +65,8 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
     const int rb0 = blockIdx.x * a.rows_wg + wv * G::RPW;
     if (rb0 < row_end) load_fibers<T, CPLX, CONTIG>(v, xp, s_base, ns, 0, rb0 + G::VE * li, lk, In, sn);
 
-    // ---- (2) sampled Khatri-Rao rows, up to four elements per thread per
-    // pass with all their factor loads issued before the products.  Loads
-    // run over the N-1 modes that take part (a uniform bound); elements past
-    // the end read element 0 and are not stored.  The product runs over the
-    // modes in order, as before.
-    {
-        const int nm = N - 1;
-        const int tot = ns * R;
-        constexpr int KE = 4;
-        const int ke = min(KE, (tot + nthr - 1) / nthr);  // passes fit the elements
-        for (int e0 = tid; e0 < tot; e0 += ke * nthr) {
-            T vr[KE][kMaxOrder - 1], vi[KE][kMaxOrder - 1];
-#pragma unroll
-            for (int h = 0; h < KE; ++h) {
-                if (h >= ke) break;  // uniform
-                const int e = min(e0 + h * nthr, tot - 1);
-                const int sl = e / R, r = e - (e / R) * R;
-#pragma unroll
-                for (int j = 0; j < kMaxOrder - 1; ++j) {
-                    if (j >= nm) break;  // uniform
-                    const int m = j < n ? j : j + 1;
-                    const T *Am = (const T *)a.A.p[m];
-                    const int64_t o = (int64_t)s_idx[sl * N + m] * R + r;
-                    if (CPLX) {
-                        vr[h][j] = Am[2 * o];
-                        vi[h][j] = Am[2 * o + 1];
-                    } else {
-                        vr[h][j] = Am[o];
-                    }
-                }
-            }
-#pragma unroll
-            for (int h = 0; h < KE; ++h) {
-                if (h >= ke) break;
-                const int e = e0 + h * nthr;
-                if (e >= tot) continue;
-                const int sl = e / R, r = e - sl * R;
-                if (!CPLX) {
-                    T z = (T)1;
-#pragma unroll
-                    for (int j = 0; j < kMaxOrder - 1; ++j)
-                        if (j < nm) z *= vr[h][j];
-                    Zr[sl * LDB + r] = z;
-                    if (WEIGHTED) Bre[sl * LDB + r] = (T)(s_w[sl] * (double)z);
-                } else {
-                    T zr = (T)1, zi = (T)0;
-#pragma unroll
-                    for (int j = 0; j < kMaxOrder - 1; ++j) {
-                        if (j >= nm) break;
-                        const T ar = vr[h][j], ai = vi[h][j];
-                        const T nr = zr * ar - zi * ai;
-                        const T ni = zr * ai + zi * ar;
-                        zr = nr;
-                        zi = ni;
-                    }
-                    // Y = X conj(Z): columns [0,R) real part, [R,2R) imaginary part
-                    Bre[sl * LDB + r] = zr;
-                    Bim[sl * LDB + r] = zi;
-                    Bre[sl * LDB + R + r] = -zi;
-                    Bim[sl * LDB + R + r] = zr;
-                }
-            }
-        }
-    }
+    // ---- (2) sampled Khatri-Rao rows
+    chunk_krp<T, CPLX, WEIGHTED>(a, ns, LDB, s_idx, s_w, Bre, Bim, Zr, tid);
     __syncthreads();
 
     // ---- (3) Gram of the chunk, V(r, q) = sum_k w_k z_k(r) z_k(q) (complex:
@@ -378,22 +191,13 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
         }
     }
 
-    // Output tile row i' of MFMA c is fiber row rowbase + VE*i' + c.  Lane l
-    // holds column 16*ct + l%16 and tile rows i' = 4*(l/16) + v (FP32
-    // 16x16x4) or i' = l/16 + 4*v (FP64 16x16x4), v = 0..3.
+    // the row group's partial products, column by column
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
         const int col = ct * 16 + li;
-        if (col >= a.ncols) continue;
-        T *dst = wp + (size_t)col * In;
-#pragma unroll
-        for (int vv = 0; vv < 4; ++vv)
-#pragma unroll
-            for (int c = 0; c < G::VE; ++c) {
-                const int ip = sizeof(T) == 8 ? lk + 4 * vv : 4 * lk + vv;
-                const int row = rowbase + G::VE * ip + c;
-                if (row < row_end) dst[row] = acc[ct][c][vv];
-            }
+        if (col < a.ncols)
+            store_group<T, G::VE>(wp + (size_t)col * In, acc[ct], rowbase, row_end, lk,
+                                  In % (sizeof(T) == 4 && G::VE == 4 ? 4 : 2) == 0);
     }
     }  // row groups
 }
@@ -401,7 +205,7 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
 // ---------------------------------------------------------------------------
 GatherPlan plan_gather_bf16(int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks);
 
-GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks) {
+GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks, int order) {
     if (kind == K_BF16) return plan_gather_bf16(R, S, In, contig_ok, max_chunks);
     GatherPlan g{};
     g.kind = kind;
@@ -422,11 +226,31 @@ GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_o
     // consumes 16 samples per iteration).
     const size_t ldb = (size_t)ldb_for(g.ct, tsize);
     auto lds_for = [&](int k) {
-        const size_t head = (((size_t)k * (16 + 4 * kMaxOrder)) + 15) & ~(size_t)15;
+        const size_t head = (((size_t)k * (16 + 4 * order)) + 15) & ~(size_t)15;
         return head + (size_t)k * ldb * tsize * 2;  // room for Bre + (Bim or Zraw)
     };
     int kc = 64;
-    if (max_chunks == 0 && S >= kWholeFiberS) {
+    const int sgw = stream_gw_host(kind, g.ct);
+    if (max_chunks == 0 && S >= kWholeFiberS && contig_ok && R <= kStreamMaxR && sgw >= 1 && In % ve == 0) {
+        // streaming form: accumulators over whole splits, one split per
+        // resident workgroup (per row block)
+        const int ks = kStreamLoads / sgw;
+        g.stream = true;
+        g.rows_wg = g.waves * sgw * rpw;
+        g.row_blocks = (int)ceil_div(In, g.rows_wg);
+        const int step = std::max(16, 4 * ks);  // KC a multiple of the batch
+        kc = 256;
+        while (kc > step && lds_for(kc) > 40 * 1024) kc -= step;  // four workgroups per CU
+        const size_t lds = lds_for(kc);
+        int splits = std::max(1, stream_cap(kind, g.ct, lds) / g.row_blocks);
+        splits = (int)std::min<int64_t>(splits, std::max<int64_t>(1, S / 64));
+        g.per_split = (int32_t)ceil_div(S, splits);
+        g.chunks = (int)ceil_div(S, g.per_split);
+        g.kc = kc;
+        g.contig = true;
+        g.lds_bytes = lds;
+        return g;
+    } else if (max_chunks == 0 && S >= kWholeFiberS) {
         // long sample sets: every workgroup reads whole fibers (all row groups)
         // of its chunk, about a thousand chunks
         g.row_blocks = 1;
@@ -504,7 +328,9 @@ hipError_t launch_gather(const GatherPlan &gp, const GatherArgs &a, hipStream_t 
     k.ncols = gp.ncols;
     k.kc = gp.kc;
     k.rows_wg = gp.rows_wg;
+    k.per_split = gp.per_split;
     const bool weighted = (a.idx && a.w) || (!a.idx && a.cdf);
+    if (gp.stream) return launch_gather_stream(gp, k, weighted, st);
     switch (gp.kind) {
         case K_F32: return launch_t<float, false>(gp, k, weighted, st);
         case K_F64: return launch_t<double, false>(gp, k, weighted, st);
