@@ -236,12 +236,21 @@ GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_o
         // resident workgroup (per row block)
         const int ks = kStreamLoads / sgw;
         g.stream = true;
-        g.rows_wg = g.waves * sgw * rpw;
-        g.row_blocks = (int)ceil_div(In, g.rows_wg);
+        // row groups dealt evenly to the fewest blocks of at most
+        // waves * sgw groups
+        const int64_t nrg = ceil_div(In, (int64_t)rpw);
+        g.row_blocks = (int)ceil_div(nrg, (int64_t)g.waves * sgw);
+        g.rows_wg = (int)(ceil_div(nrg, (int64_t)g.row_blocks) * rpw);
+        // LDS: indices, then real B tiles (two with weights) or the
+        // interleaved complex rows
+        auto lds_stream = [&](int k) {
+            const size_t head = (((size_t)k * (16 + 4 * order)) + 15) & ~(size_t)15;
+            return cplx ? head + (size_t)k * stream_ldz(R, tsize) * tsize : head + (size_t)k * ldb * tsize * 2;
+        };
         const int step = std::max(16, 4 * ks);  // KC a multiple of the batch
         kc = 256;
-        while (kc > step && lds_for(kc) > 40 * 1024) kc -= step;  // four workgroups per CU
-        const size_t lds = lds_for(kc);
+        while (kc > step && lds_stream(kc) > 40 * 1024) kc -= step;  // four workgroups per CU
+        const size_t lds = lds_stream(kc);
         int splits = std::max(1, stream_cap(kind, g.ct, lds) / g.row_blocks);
         splits = (int)std::min<int64_t>(splits, std::max<int64_t>(1, S / 64));
         g.per_split = (int32_t)ceil_div(S, splits);

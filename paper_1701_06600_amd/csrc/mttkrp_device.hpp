@@ -119,9 +119,14 @@ __device__ __forceinline__ void chunk_indices(const KArgs &a, uint64_t tt, int s
         if (sl < ns) {
             const int64_t s = (int64_t)s0 + sl;
             if (a.idx) {
+                // every slot loaded (past the order: slot 0 again, the same
+                // line), then selected: no branch between the loads, which
+                // stay in flight together
+                int32_t iv[kMaxOrder];
 #pragma unroll
-                for (int m = 0; m < kMaxOrder; ++m)
-                    if (m < N) row[m] = (m == n) ? 0 : a.idx[s * N + m];
+                for (int m = 0; m < kMaxOrder; ++m) iv[m] = a.idx[s * N + (m < N ? m : 0)];
+#pragma unroll
+                for (int m = 0; m < kMaxOrder; ++m) row[m] = (m < N && m != n) ? iv[m] : 0;
                 if (a.w) wv = a.w[s];
             } else {
                 wv = draw_sample(a.mi, a.seed, tt, s, a.cdf, a.use_cdf != 0, row);
@@ -150,11 +155,14 @@ __device__ __forceinline__ void chunk_indices_given(const KArgs &a, int s0, int 
     for (int sl = tid; sl < KC; sl += blockDim.x) {
         const bool in = sl < ns;
         const int64_t s = (int64_t)s0 + (in ? sl : 0);
+        int32_t iv[kMaxOrder];
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m) iv[m] = a.idx[s * N + (m < N ? m : 0)];  // no branch between loads
         int64_t base = 0;
 #pragma unroll
         for (int m = 0; m < kMaxOrder; ++m) {
             if (m >= N) break;  // uniform
-            const int32_t i = (in && m != n) ? a.idx[s * N + m] : 0;
+            const int32_t i = (in && m != n) ? iv[m] : 0;
             s_idx[sl * N + m] = i;
             base += (int64_t)i * a.mi.strides[m];
         }
@@ -164,76 +172,174 @@ __device__ __forceinline__ void chunk_indices_given(const KArgs &a, int s0, int 
 }
 
 // (2) Sampled Khatri-Rao rows of the chunk's ns samples into the B operand
-// tiles, up to four elements per thread per pass with all their factor loads
-// issued before the products.  Loads run over the N-1 modes that take part
-// (a uniform bound); elements past the end read element 0 and are not
-// stored.  The product runs over the modes in order.  Real data: Zr gets the
-// raw rows and (weighted) Bre the rows scaled by the sample weights; complex
-// data: Y = X conj(Z) takes columns [0, R) real part, [R, 2R) imaginary part.
-template <typename T, bool CPLX, bool WEIGHTED, int KE = 4>
-__device__ __forceinline__ void chunk_krp(const KArgs &a, int ns, int LDB, const int32_t *s_idx, const double *s_w,
-                                          T *Bre, T *Bim, T *Zr, int tid) {
+// tiles, KE elements per thread per pass; each row is the product of the
+// N-1 participating factor rows, taken over the modes in order.  Real data:
+// Zr gets the raw rows and (weighted) Bre the rows scaled by the sample
+// weights; complex data: Y = X conj(Z) takes columns [0, R) real part,
+// [R, 2R) imaginary part.  ILV (complex only): row sl of Bre (stride LDB)
+// holds the B operand pairs of its columns interleaved, (zr, zi) of column r
+// at 2 r and (-zi, zr) of column R + r at 2 (R + r), with a zero pair at 4R
+// for the padding columns.
+//
+// Mode-by-mode form (for kernels whose accumulators stay live meanwhile):
+// per pass, the KE elements' factor values of one mode are loaded and
+// multiplied in before the next mode's are loaded, so that the registers do
+// not grow with the order; the products run over the modes in the same
+// order as in chunk_krp (bit-identical rows).
+template <typename T, bool CPLX, bool WEIGHTED, int KE, bool ILV>
+__device__ __forceinline__ void chunk_krp_by_mode(const KArgs &a, int ns, int LDB, const int32_t *s_idx,
+                                                  const double *s_w, T *Bre, T *Bim, T *Zr, int tid) {
     const int N = a.mi.order, n = a.mi.n, R = a.R;
     const int nthr = blockDim.x;
     const int nm = N - 1;
     const int tot = ns * R;
-    // factor of the j-th mode that takes part, chosen by compares (a runtime
-    // index into the argument's pointer array would copy it to scratch)
-    const T *Aj[kMaxOrder - 1];
-#pragma unroll
-    for (int j = 0; j < kMaxOrder - 1; ++j) Aj[j] = (const T *)(j < n ? a.A.p[j] : a.A.p[j + 1]);
-    const int ke = min(KE, (tot + nthr - 1) / nthr);  // passes fit the elements
-    for (int e0 = tid; e0 < tot; e0 += ke * nthr) {
-        T vr[KE][kMaxOrder - 1], vi[KE][kMaxOrder - 1];
+    // always KE elements per pass (past the end: the last element again,
+    // not stored), so that no branch separates their loads
+    for (int e0 = tid; e0 < tot; e0 += KE * nthr) {
+        T zr[KE], zi[KE];
 #pragma unroll
         for (int h = 0; h < KE; ++h) {
-            if (h >= ke) break;  // uniform
-            const int e = min(e0 + h * nthr, tot - 1);
-            const int sl = e / R, r = e - (e / R) * R;
+            zr[h] = (T)1;
+            zi[h] = (T)0;
+        }
 #pragma unroll
-            for (int j = 0; j < kMaxOrder - 1; ++j) {
-                if (j >= nm) break;  // uniform
-                const int m = j < n ? j : j + 1;
-                const T *Am = Aj[j];
+        for (int j = 0; j < kMaxOrder - 1; ++j) {
+            if (j >= nm) break;  // uniform
+            const int m = j < n ? j : j + 1;
+            const T *Am = (const T *)(j < n ? a.A.p[j] : a.A.p[j + 1]);
+            T ar[KE], ai[KE];
+#pragma unroll
+            for (int h = 0; h < KE; ++h) {
+                const int e = min(e0 + h * nthr, tot - 1);
+                const int sl = e / R, r = e - (e / R) * R;
                 const int64_t o = (int64_t)s_idx[sl * N + m] * R + r;
                 if (CPLX) {
-                    vr[h][j] = Am[2 * o];
-                    vi[h][j] = Am[2 * o + 1];
+                    ar[h] = Am[2 * o];
+                    ai[h] = Am[2 * o + 1];
                 } else {
-                    vr[h][j] = Am[o];
+                    ar[h] = Am[o];
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < KE; ++h) {
+                if (!CPLX) {
+                    zr[h] *= ar[h];
+                } else {
+                    const T nr = zr[h] * ar[h] - zi[h] * ai[h];
+                    const T ni = zr[h] * ai[h] + zi[h] * ar[h];
+                    zr[h] = nr;
+                    zi[h] = ni;
                 }
             }
         }
 #pragma unroll
         for (int h = 0; h < KE; ++h) {
-            if (h >= ke) break;
+            const int e = e0 + h * nthr;
+            if (e >= tot) continue;
+            const int sl = e / R, r = e - sl * R;
+            if (!CPLX) {
+                Zr[sl * LDB + r] = zr[h];
+                if (WEIGHTED) Bre[sl * LDB + r] = (T)(s_w[sl] * (double)zr[h]);
+            } else if (ILV) {
+                Bre[sl * LDB + 2 * r] = zr[h];
+                Bre[sl * LDB + 2 * r + 1] = zi[h];
+                Bre[sl * LDB + 2 * (R + r)] = -zi[h];
+                Bre[sl * LDB + 2 * (R + r) + 1] = zr[h];
+            } else {
+                Bre[sl * LDB + r] = zr[h];
+                Bim[sl * LDB + r] = zi[h];
+                Bre[sl * LDB + R + r] = -zi[h];
+                Bim[sl * LDB + R + r] = zr[h];
+            }
+        }
+    }
+}
+
+// All N-1 modes at once (NM of them, a compile-time count): the KE
+// elements' factor loads of every mode are issued together, one round trip
+// per pass; always KE elements per pass (past the end: the last element
+// again, not stored).
+template <typename T, bool CPLX, bool WEIGHTED, int KE, bool ILV, int NM>
+__device__ __forceinline__ void krp_modes(const KArgs &a, int ns, int LDB, const int32_t *s_idx, const double *s_w,
+                                          T *Bre, T *Bim, T *Zr, int tid) {
+    const int N = a.mi.order, n = a.mi.n, R = a.R;
+    const int nthr = blockDim.x;
+    const int tot = ns * R;
+    // factor of the j-th mode that takes part, chosen by compares (a runtime
+    // index into the argument's pointer array would copy it to scratch)
+    const T *Aj[NM];
+    int mj[NM];
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+        mj[j] = j < n ? j : j + 1;
+        Aj[j] = (const T *)(j < n ? a.A.p[j] : a.A.p[j + 1]);
+    }
+    for (int e0 = tid; e0 < tot; e0 += KE * nthr) {
+        T vr[KE][NM], vi[KE][NM];
+#pragma unroll
+        for (int h = 0; h < KE; ++h) {
+            const int e = min(e0 + h * nthr, tot - 1);
+            const int sl = e / R, r = e - (e / R) * R;
+#pragma unroll
+            for (int j = 0; j < NM; ++j) {
+                const int64_t o = (int64_t)s_idx[sl * N + mj[j]] * R + r;
+                if (CPLX) {
+                    vr[h][j] = Aj[j][2 * o];
+                    vi[h][j] = Aj[j][2 * o + 1];
+                } else {
+                    vr[h][j] = Aj[j][o];
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < KE; ++h) {
             const int e = e0 + h * nthr;
             if (e >= tot) continue;
             const int sl = e / R, r = e - sl * R;
             if (!CPLX) {
                 T z = (T)1;
 #pragma unroll
-                for (int j = 0; j < kMaxOrder - 1; ++j)
-                    if (j < nm) z *= vr[h][j];
+                for (int j = 0; j < NM; ++j) z *= vr[h][j];
                 Zr[sl * LDB + r] = z;
                 if (WEIGHTED) Bre[sl * LDB + r] = (T)(s_w[sl] * (double)z);
             } else {
                 T zr = (T)1, zi = (T)0;
 #pragma unroll
-                for (int j = 0; j < kMaxOrder - 1; ++j) {
-                    if (j >= nm) break;
+                for (int j = 0; j < NM; ++j) {
                     const T ar = vr[h][j], ai = vi[h][j];
                     const T nr = zr * ar - zi * ai;
                     const T ni = zr * ai + zi * ar;
                     zr = nr;
                     zi = ni;
                 }
-                Bre[sl * LDB + r] = zr;
-                Bim[sl * LDB + r] = zi;
-                Bre[sl * LDB + R + r] = -zi;
-                Bim[sl * LDB + R + r] = zr;
+                if (ILV) {
+                    Bre[sl * LDB + 2 * r] = zr;
+                    Bre[sl * LDB + 2 * r + 1] = zi;
+                    Bre[sl * LDB + 2 * (R + r)] = -zi;
+                    Bre[sl * LDB + 2 * (R + r) + 1] = zr;
+                } else {
+                    Bre[sl * LDB + r] = zr;
+                    Bim[sl * LDB + r] = zi;
+                    Bre[sl * LDB + R + r] = -zi;
+                    Bim[sl * LDB + R + r] = zr;
+                }
             }
         }
+    }
+}
+
+template <typename T, bool CPLX, bool WEIGHTED, int KE = 4, bool ILV = false>
+__device__ __forceinline__ void chunk_krp(const KArgs &a, int ns, int LDB, const int32_t *s_idx, const double *s_w,
+                                          T *Bre, T *Bim, T *Zr, int tid) {
+    static_assert(kMaxOrder == 8, "one case per count of participating modes");
+    switch (a.mi.order - 1) {  // uniform
+        case 1: krp_modes<T, CPLX, WEIGHTED, KE, ILV, 1>(a, ns, LDB, s_idx, s_w, Bre, Bim, Zr, tid); break;
+        case 2: krp_modes<T, CPLX, WEIGHTED, KE, ILV, 2>(a, ns, LDB, s_idx, s_w, Bre, Bim, Zr, tid); break;
+        case 3: krp_modes<T, CPLX, WEIGHTED, KE, ILV, 3>(a, ns, LDB, s_idx, s_w, Bre, Bim, Zr, tid); break;
+        case 4: krp_modes<T, CPLX, WEIGHTED, KE, ILV, 4>(a, ns, LDB, s_idx, s_w, Bre, Bim, Zr, tid); break;
+        case 5: krp_modes<T, CPLX, WEIGHTED, KE, ILV, 5>(a, ns, LDB, s_idx, s_w, Bre, Bim, Zr, tid); break;
+        case 6: krp_modes<T, CPLX, WEIGHTED, KE, ILV, 6>(a, ns, LDB, s_idx, s_w, Bre, Bim, Zr, tid); break;
+        default: krp_modes<T, CPLX, WEIGHTED, KE, ILV, 7>(a, ns, LDB, s_idx, s_w, Bre, Bim, Zr, tid); break;
     }
 }
 
@@ -284,6 +390,12 @@ __device__ __forceinline__ void store_group(T *dst, const Acc (&acc)[VE], int rb
 // Streaming form (mttkrp_stream.hip): row groups per wave for a plan (0 when
 // the accumulators exceed the register budget), the workgroups the chip
 // holds at once, and the launch.
+// row stride (in T) of the interleaved complex B operand rows in LDS:
+// 4R + 2, padded when rows would start on the same LDS bank
+__host__ __device__ inline int stream_ldz(int R, int tsize) {
+    const int ld = 4 * R + 2;
+    return (ld * tsize / 4) % 32 == 0 ? ld + 2 : ld;
+}
 constexpr int kStreamLoads = 8;   // loads per batch (per lane, 16 bytes each)
 constexpr int kStreamMaxR = 32;   // Gram: at most three tiles, one per wave
 int stream_gw_host(int kind, int ct);

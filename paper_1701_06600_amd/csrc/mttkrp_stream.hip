@@ -58,12 +58,15 @@ __global__ __launch_bounds__(256) void gather_stream(KArgs a) {
     int64_t *s_base = (int64_t *)lds;
     double *s_w = (double *)(s_base + KC);
     int32_t *s_idx = (int32_t *)(s_w + KC);
+    // Real data: B operand tiles (row stride LDB; weighted: the raw rows in
+    // Zr after them).  Complex data: per sample, the B operand pairs of the
+    // 2R columns interleaved, then a zero pair (row stride LDZ).
+    const int LDZ = CPLX ? stream_ldz(R, (int)sizeof(T)) : LDB;
     T *Bre = (T *)(lds + (((size_t)KC * (16 + 4 * N) + 15) & ~(size_t)15));
-    T *Bim = Bre + (size_t)KC * LDB;
-    T *Zr = CPLX ? Bre : (WEIGHTED ? Bre + (size_t)KC * LDB : Bre);
+    T *Zr = WEIGHTED ? Bre + (size_t)KC * LDB : Bre;
     {
         // padding columns stay zero; sample rows are rewritten per chunk
-        const int words = (int)(((size_t)KC * LDB * sizeof(T) * ((CPLX || WEIGHTED) ? 2 : 1)) / 4);
+        const int words = (int)(((size_t)KC * LDZ * sizeof(T) * (WEIGHTED ? 2 : 1)) / 4);
         uint32_t *p = (uint32_t *)Bre;
         for (int e = tid; e < words; e += blockDim.x) p[e] = 0u;
     }
@@ -96,6 +99,12 @@ __global__ __launch_bounds__(256) void gather_stream(KArgs a) {
     const int kk0 = nt16 == 1 ? wv : 0, kkstep = nt16 == 1 ? 4 : 1;
     v4d gacc = {0.0, 0.0, 0.0, 0.0};
 
+    int zoff[CT];  // complex: this lane's B pair of column tile ct (the zero pair past 2R)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int col = ct * 16 + li;
+        zoff[ct] = col < 2 * R ? 2 * col : 4 * R;
+    }
     T v[KS][GW][G::NV];
     // The chunk's products: batches of k-steps ks .. ks + 4 KS - 1, lane
     // (li, lk) taking sample ks + 4 k + lk and rows VE li .. VE li + VE - 1
@@ -139,8 +148,15 @@ __global__ __launch_bounds__(256) void gather_stream(KArgs a) {
                 const int sl = ks + 4 * k + lk;  // < KC: KC is a multiple of 4 KS
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) {
-                    const T bre = Bre[sl * LDB + ct * 16 + li];
-                    const T bim = CPLX ? Bim[sl * LDB + ct * 16 + li] : (T)0;
+                    T bre, bim = (T)0;
+                    if (!CPLX) {
+                        bre = Bre[sl * LDB + ct * 16 + li];
+                    } else {
+                        // column c < R: (zr, zi) of c; R <= c < 2R: (-zi, zr)
+                        // of c - R (the imaginary part of X conj z)
+                        bre = Bre[sl * LDZ + zoff[ct]];
+                        bim = Bre[sl * LDZ + zoff[ct] + 1];
+                    }
 #pragma unroll
                     for (int g = 0; g < GW; ++g) {
 #pragma unroll
@@ -167,7 +183,9 @@ __global__ __launch_bounds__(256) void gather_stream(KArgs a) {
         const bool in = c0n < sb && tc < min(KC, sb - c0n);
         const int64_t s = in ? (int64_t)c0n + tc : 0;
 #pragma unroll
-        for (int m = 0; m < kMaxOrder; ++m) pidx[m] = (in && m < N && m != n) ? a.idx[s * N + m] : 0;
+        for (int m = 0; m < kMaxOrder; ++m) pidx[m] = a.idx[s * N + (m < N ? m : 0)];  // no branch between loads
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m) pidx[m] = (in && m < N && m != n) ? pidx[m] : 0;
         pw = in ? (a.w ? a.w[s] : 1.0) : 0.0;
     };
     fetch(sa, tid);
@@ -194,17 +212,12 @@ __global__ __launch_bounds__(256) void gather_stream(KArgs a) {
         }
         __syncthreads();
         fetch(c0 + KC, tc);
-        // four elements per pass (two for FP64 and complex data, whose factor
-        // values take twice the registers; the accumulators sit in AGPRs
-        // meanwhile)
-        chunk_krp<T, CPLX, WEIGHTED, (sizeof(T) == 8 || CPLX) ? 2 : 4>(a, ns, LDB, s_idx, s_w, Bre, Bim, Zr, tc);
+        // mode by mode, four elements per pass (the accumulators stay live)
+        chunk_krp_by_mode<T, CPLX, WEIGHTED, 4, true>(a, ns, LDZ, s_idx, s_w, Bre, nullptr, Zr, tc);
         if (ns < KC) {
             // B operand rows past the chunk: zero (their lanes read real fibers)
-            const int e0 = ns * LDB, e1 = KC * LDB;
-            for (int e = e0 + tc; e < e1; e += blockDim.x) {
-                Bre[e] = (T)0;
-                if (CPLX) Bim[e] = (T)0;
-            }
+            const int e0 = ns * LDZ, e1 = KC * LDZ;
+            for (int e = e0 + tc; e < e1; e += blockDim.x) Bre[e] = (T)0;
         }
         __syncthreads();
         if (gram) {
@@ -220,10 +233,10 @@ __global__ __launch_bounds__(256) void gather_stream(KArgs a) {
                     const double bv = (qin && sin) ? (double)Zr[sl * LDB + q] : 0.0;
                     gacc = mfma16(av, bv, gacc);
                 } else {
-                    gacc = mfma16((rin && sin) ? (double)Bre[sl * LDB + r] : 0.0,
-                                  (qin && sin) ? (double)Bre[sl * LDB + q] : 0.0, gacc);
-                    gacc = mfma16((rin && sin) ? (double)Bim[sl * LDB + r] : 0.0,
-                                  (qin && sin) ? (double)Bim[sl * LDB + q] : 0.0, gacc);
+                    gacc = mfma16((rin && sin) ? (double)Bre[sl * LDZ + 2 * r] : 0.0,
+                                  (qin && sin) ? (double)Bre[sl * LDZ + 2 * q] : 0.0, gacc);
+                    gacc = mfma16((rin && sin) ? (double)Bre[sl * LDZ + 2 * r + 1] : 0.0,
+                                  (qin && sin) ? (double)Bre[sl * LDZ + 2 * q + 1] : 0.0, gacc);
                 }
             }
         }
