@@ -206,6 +206,8 @@ struct StepArgs {
     int32_t *info;          // set to CPRAND_W_PINV when the pseudo-inverse was used
 };
 size_t step_finish_lds(int32_t In, int32_t R, bool mix);
+constexpr int kMaxParts = 8;  // partial products the one-workgroup finish sums (the fused gathers' chunk cap)
+
 // Under mixing only A-hat and lambda are written (A is left untouched).
 hipError_t launch_step_finish(const StepArgs &a, bool dbl, hipStream_t st);
 hipError_t launch_normalize(int32_t In, int32_t R, void *A, bool adouble,

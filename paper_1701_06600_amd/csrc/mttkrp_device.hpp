@@ -63,10 +63,37 @@ struct KArgs {
 
 // Fiber values of one MFMA batch: lane (li, lk) takes sample ks + 4u + lk
 // (u < kUnroll) and rows row0 .. row0 + VE - 1 of its mode-n fiber.
+// fast (contiguous fibers, I_n % VE == 0): every load unconditional, no
+// branch between them, so all stay in flight together; a lane past the
+// chunk reads the chunk's last fiber (its B operand row is zero) and a row
+// past the fiber reads the fiber's last vector (output rows that are never
+// stored: each MFMA output row depends only on its own A row).
 template <typename T, bool CPLX, bool CONTIG>
 __device__ __forceinline__ void load_fibers(T (&v)[kUnroll][16 / sizeof(T)], const T *xp, const int64_t *s_base,
-                                            int ns, int ks, int row0, int lk, int In, int64_t sn) {
+                                            int ns, int ks, int row0, int lk, int In, int64_t sn, bool fast) {
     typedef Geo<T, CPLX> G;
+    if (CONTIG && fast) {
+        int64_t b[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) b[u] = s_base[min(ks + 4 * u + lk, ns - 1)];
+        const int rc = min(row0, In - G::VE);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const T *src = xp + (b[u] + rc) * (CPLX ? 2 : 1);
+            if (sizeof(T) == 4) {
+                const float4 q = *(const float4 *)src;
+                v[u][0] = q.x;
+                v[u][1] = q.y;
+                v[u][2] = q.z;
+                v[u][3] = q.w;
+            } else {
+                const double2 q = *(const double2 *)src;
+                v[u][0] = q.x;
+                v[u][1] = q.y;
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
         const int sl = ks + 4 * u + lk;
@@ -387,6 +414,194 @@ __device__ __forceinline__ void store_group(T *dst, const Acc (&acc)[VE], int rb
     }
 }
 
+// The chunked MTTKRP of one workgroup (chunk blockIdx.y, row block
+// blockIdx.x; see mttkrp.hip): W partial products of the chunk's rows into
+// a.wpart, and Gram entries p (row-major R x R) with p mod gram_nrb ==
+// gram_rb (R <= 16; for larger R, 16 x 16 tiles dealt likewise over
+// (gram_rb, wave) pairs) into vp.  gram_nrb = 1 computes the whole Gram.
+template <typename T, bool CPLX, int CT, bool CONTIG, bool WEIGHTED>
+__device__ __forceinline__ void gather_chunk(const KArgs &a, unsigned char *lds, double *vp, int gram_rb,
+                                             int gram_nrb) {
+    typedef Geo<T, CPLX> G;
+    typedef typename AccT<T>::type Acc;
+    constexpr int LDB = ldb_for(CT, (int)sizeof(T));
+
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int KC = a.kc;
+    const int N = a.mi.order, n = a.mi.n;
+    const int R = a.R;
+    const int chunk = blockIdx.y;
+    const int s0 = chunk * KC;
+    const int ns = min(KC, a.S - s0);
+
+    // ---- LDS carve-up
+    int64_t *s_base = (int64_t *)lds;                      // KC
+    double *s_w = (double *)(s_base + KC);                 // KC
+    int32_t *s_idx = (int32_t *)(s_w + KC);                // KC x N
+    T *Bre = (T *)(lds + (((size_t)KC * (16 + 4 * N) + 15) & ~(size_t)15));
+    T *Bim = Bre + (size_t)KC * LDB;                       // complex only
+    T *Zr = CPLX ? Bre : (WEIGHTED ? Bre + (size_t)KC * LDB : Bre);  // raw z (real)
+
+    // ---- (1) indices, weights and fiber offsets
+    const uint64_t tt = a.t_dev ? *a.t_dev : a.t;
+    chunk_indices(a, tt, s0, ns, KC, s_base, s_w, s_idx, tid);
+    // zero the B operand tiles (padding columns and samples stay zero)
+    {
+        const int words = (int)(((size_t)KC * LDB * sizeof(T) * ((CPLX || WEIGHTED) ? 2 : 1)) / 4);
+        uint32_t *p = (uint32_t *)Bre;
+        for (int e = tid; e < words; e += nthr) p[e] = 0u;
+    }
+    __syncthreads();
+
+    // ---- fiber loads (phase 4 below): the first batch of this wave's first
+    // row group is issued now, so its latency overlaps the Khatri-Rao loads
+    const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+    const int In = a.In;
+    const int row_end = min(In, (int)(blockIdx.x + 1) * a.rows_wg);
+    const T *xp = (const T *)a.X;
+    const int64_t sn = a.mi.strides[n];
+    T v[kUnroll][G::NV];
+    const bool fast = In % G::VE == 0;
+    const int rb0 = blockIdx.x * a.rows_wg + wv * G::RPW;
+    if (rb0 < row_end) load_fibers<T, CPLX, CONTIG>(v, xp, s_base, ns, 0, rb0 + G::VE * li, lk, In, sn, fast);
+
+    // ---- (2) sampled Khatri-Rao rows
+    chunk_krp<T, CPLX, WEIGHTED>(a, ns, LDB, s_idx, s_w, Bre, Bim, Zr, tid);
+    __syncthreads();
+
+    // ---- (3) Gram of the chunk, V(r, q) = sum_k w_k z_k(r) z_k(q) (complex:
+    // zr zr^T + zi zi^T) over the chunk's samples k, FP64, fixed order.
+    // No barrier: waves without Gram work go on to the fiber products.
+    const int nrb = gram_nrb, rb = gram_rb;
+    if (R <= 16) {
+        // one output tile: entries p = (r, q) dealt to the chunk's row blocks
+        // (p mod row blocks); tpp lanes share an entry, each summing every
+        // tpp-th sample, and a shuffle tree over the tpp lanes closes the sum
+        const int nmine = (R * R - rb + nrb - 1) / nrb;  // entries of this block
+        int tpp = 1;
+        while (tpp < 16 && 2 * tpp * nmine <= nthr) tpp *= 2;
+        const int per = nthr / tpp;  // entries per pass
+        for (int base = 0; base < nmine; base += per) {
+            const int k = base + tid / tpp, part = tid & (tpp - 1);
+            const int p = rb + nrb * k;
+            const int r = p / R, q = p - (p / R) * R;
+            const bool act = k < nmine && q >= r;
+            double acc = 0.0;
+            if (act) {
+                for (int sl = part; sl < ns; sl += tpp) {
+                    if (!CPLX) {
+                        double t = (double)Zr[sl * LDB + r] * (double)Zr[sl * LDB + q];
+                        if (WEIGHTED) t *= s_w[sl];
+                        acc += t;
+                    } else {
+                        acc += (double)Bre[sl * LDB + r] * (double)Bre[sl * LDB + q] +
+                               (double)Bim[sl * LDB + r] * (double)Bim[sl * LDB + q];
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1)
+                if (o < tpp) acc += __shfl_xor(acc, o, 64);  // uniform: tpp is the same in every lane
+            if (act && part == 0) {
+                vp[r * R + q] = acc;
+                vp[q * R + r] = acc;
+            }
+        }
+    } else {
+        // FP64 MFMA 16x16x4: output tiles (rt, qt), qt >= rt, dealt to the
+        // chunk's (row block, wave) pairs.  Lane (li, lk) feeds A(r = 16 rt +
+        // li, k = 4 kk + lk) and B(k, q = 16 qt + li) and holds rows 16 rt + lk
+        // + 4 v of column 16 qt + li.  Columns at or past R are masked (for
+        // complex data they hold the imaginary block).
+        const int wv3 = tid >> 6, l3 = tid & 63, li3 = l3 & 15, lk3 = l3 >> 4;
+        const int nwv = nthr >> 6;
+        const int nt16 = (R + 15) / 16;
+        const int ntiles = nt16 * (nt16 + 1) / 2;
+        const int ksteps = (ns + 3) / 4;  // rows past ns are zero (and have zero weight)
+        for (int tix = rb + nrb * wv3; tix < ntiles; tix += nrb * nwv) {  // uniform per wave
+            int rt = 0, rem = tix;
+            while (rem >= nt16 - rt) {
+                rem -= nt16 - rt;
+                ++rt;
+            }
+            const int qt = rt + rem;
+            const int r = rt * 16 + li3, q = qt * 16 + li3;
+            const bool rin = r < R, qin = q < R;
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+            for (int kk = 0; kk < ksteps; ++kk) {
+                const int sl = 4 * kk + lk3;
+                if (!CPLX) {
+                    double av = rin ? (double)Zr[sl * LDB + r] : 0.0;
+                    if (WEIGHTED) av *= s_w[sl];
+                    const double bv = qin ? (double)Zr[sl * LDB + q] : 0.0;
+                    acc = mfma16(av, bv, acc);
+                } else {
+                    acc = mfma16(rin ? (double)Bre[sl * LDB + r] : 0.0, qin ? (double)Bre[sl * LDB + q] : 0.0, acc);
+                    acc = mfma16(rin ? (double)Bim[sl * LDB + r] : 0.0, qin ? (double)Bim[sl * LDB + q] : 0.0, acc);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = rt * 16 + lk3 + 4 * v, qq = qt * 16 + li3;
+                if (rr < R && qq < R) {
+                    vp[rr * R + qq] = acc[v];
+                    if (rt != qt) vp[qq * R + rr] = acc[v];
+                }
+            }
+        }
+    }
+
+    // ---- (4) fibers x Z_S on MFMA, one row group of G::RPW rows per wave at a
+    // time (a workgroup covers rows_wg rows: one group per wave for short
+    // sample chunks, whole fibers for long ones)
+    T *wp = (T *)a.wpart + (size_t)chunk * a.ncols * In;
+    bool preloaded = rb0 < row_end;
+    for (int rowbase = rb0; rowbase < row_end; rowbase += (int)(blockDim.x >> 6) * G::RPW) {
+    const int row0 = rowbase + G::VE * li;
+
+    Acc acc[CT][G::VE];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int c = 0; c < G::VE; ++c) acc[ct][c] = Acc{0, 0, 0, 0};
+
+    for (int ks = 0; ks < ns; ks += 4 * kUnroll) {
+        if (!preloaded) load_fibers<T, CPLX, CONTIG>(v, xp, s_base, ns, ks, row0, lk, In, sn, fast);
+        preloaded = false;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (ks + 4 * u >= ns) break;  // uniform: the rest of this pass is past the chunk
+            const int sl = ks + 4 * u + lk;  // < KC: KC is a multiple of 4 and ns <= KC
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const T bre = Bre[sl * LDB + ct * 16 + li];
+                if (!CPLX) {
+#pragma unroll
+                    for (int c = 0; c < G::VE; ++c) acc[ct][c] = mfma16(v[u][c], bre, acc[ct][c]);
+                } else {
+                    const T bim = Bim[sl * LDB + ct * 16 + li];
+#pragma unroll
+                    for (int c = 0; c < G::VE; ++c) {
+                        acc[ct][c] = mfma16(v[u][2 * c], bre, acc[ct][c]);
+                        acc[ct][c] = mfma16(v[u][2 * c + 1], bim, acc[ct][c]);
+                    }
+                }
+            }
+        }
+    }
+
+    // the row group's partial products, column by column
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int col = ct * 16 + li;
+        if (col < a.ncols)
+            store_group<T, G::VE>(wp + (size_t)col * In, acc[ct], rowbase, row_end, lk,
+                                  In % (sizeof(T) == 4 && G::VE == 4 ? 4 : 2) == 0);
+    }
+    }  // row groups
+}
+
 // Streaming form (mttkrp_stream.hip): row groups per wave for a plan (0 when
 // the accumulators exceed the register budget), the workgroups the chip
 // holds at once, and the launch.
@@ -398,6 +613,7 @@ __host__ __device__ inline int stream_ldz(int R, int tsize) {
 }
 constexpr int kStreamLoads = 8;   // loads per batch (per lane, 16 bytes each)
 constexpr int kStreamMaxR = 32;   // Gram: at most three tiles, one per wave
+KArgs make_kargs(const GatherPlan &gp, const GatherArgs &a);
 int stream_gw_host(int kind, int ct);
 int stream_cap(int kind, int ct, size_t lds);
 hipError_t launch_gather_stream(const GatherPlan &gp, const KArgs &k, bool weighted, hipStream_t st);

@@ -33,7 +33,6 @@ template <>
 struct Pair<double> {
     typedef double2 type;
 };
-constexpr int kMaxParts = 8;  // partial products summed here (the gathers use at most this many chunks)
 constexpr int kMixGroups = 3; // mixed products: (column, VL rows) groups per thread per pass, loads in flight together
 static_assert(kColParts * kMaxRank >= kStepThreads, "tmp holds one double per thread");
 
