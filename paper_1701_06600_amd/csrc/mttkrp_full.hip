@@ -86,12 +86,42 @@ __global__ __launch_bounds__(kWaves * 64) void full_mttkrp_kernel(FullArgs a) {
     const int rw = blockIdx.x * a.rows_wg + wv * G::RPW;  // first row of this wave
     const T *X = (const T *)a.X;
     const int64_t J = a.J, JI = a.J * (int64_t)In;
+    const bool small = a.Q < (int64_t)INT32_MAX;  // 32-bit column arithmetic
 
     Acc acc[CT][VE];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
         for (int c = 0; c < VE; ++c) acc[ct][c] = Acc{0, 0, 0, 0};
+
+    // IV, VEC: load u of a tile (columns q0 + 4u + lk, rows rw + VE li ..),
+    // unconditional (I_n % VE == 0 here): a column past the tile reads its
+    // last column (its Khatri-Rao row is zero), a row past the fiber the
+    // fiber's last vector (rows never stored).  Each tile's loads are issued
+    // while the previous tile's products run: right after the MFMAs have
+    // read v[u], v[u] is loaded with the next tile's vector.
+    T v[16][VE];
+    const bool wave_rows = rw < In;  // uniform per wave
+    const int rc = min(rw + VE * (tid & 15), In - VE);
+    auto load_iv = [&](int u, int64_t q0t, int nqt) {
+        const T *src = X + (q0t + min(4 * u + lk, nqt - 1)) * (int64_t)In + rc;
+        if constexpr (sizeof(T) == 4) {
+            const float4 x = *(const float4 *)src;
+            v[u][0] = x.x;
+            v[u][1] = x.y;
+            v[u][2] = x.z;
+            v[u][3] = x.w;
+        } else {
+            const double2 x = *(const double2 *)src;
+            v[u][0] = x.x;
+            v[u][1] = x.y;
+        }
+    };
+    if (IV && VEC && wave_rows && qa < qb) {
+        const int nq0 = (int)min((int64_t)kQT, qb - qa);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) load_iv(u, qa, nq0);
+    }
 
     for (int64_t q0 = qa; q0 < qb; q0 += kQT) {
         const int nq = (int)min((int64_t)kQT, qb - q0);
@@ -100,8 +130,9 @@ __global__ __launch_bounds__(kWaves * 64) void full_mttkrp_kernel(FullArgs a) {
         // t (16 / VE) + s covers row tile t (rows rw + 16 t + li) and columns
         // q0 + 4 VE s + VE lk + c.  Both: 16 VE values per lane.
         constexpr int QS = 16 / VE;  // QV steps per tile
-        T v[16][VE];
-        if (IV) {
+        if (IV && VEC) {
+            // already in flight (issued with the previous tile's products)
+        } else if (IV) {
             const int row0 = rw + VE * li;
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
@@ -126,6 +157,31 @@ __global__ __launch_bounds__(kWaves * 64) void full_mttkrp_kernel(FullArgs a) {
 #pragma unroll
                         for (int c = 0; c < VE; ++c)
                             if (row0 + c < In) v[u][c] = src[c];
+                    }
+                }
+            }
+        } else if (VEC) {
+            // unconditional loads along j (J % VE == 0, so every tile and the
+            // tile's column count are multiples of VE): clamped as above
+#pragma unroll
+            for (int t = 0; t < VE; ++t) {
+                const int row = min(rw + 16 * t + li, In - 1);
+#pragma unroll
+                for (int s = 0; s < QS; ++s) {
+                    const int u = QS * t + s;
+                    const int64_t q = q0 + min(4 * VE * s + VE * lk, nq - VE);
+                    const int64_t k = small ? (int64_t)((uint32_t)q / (uint32_t)J) : q / J;
+                    const T *src = X + (q - k * J) + J * (int64_t)row + JI * k;
+                    if constexpr (sizeof(T) == 4) {
+                        const float4 x = *(const float4 *)src;
+                        v[u][0] = x.x;
+                        v[u][1] = x.y;
+                        v[u][2] = x.z;
+                        v[u][3] = x.w;
+                    } else {
+                        const double2 x = *(const double2 *)src;
+                        v[u][0] = x.x;
+                        v[u][1] = x.y;
                     }
                 }
             }
@@ -169,46 +225,73 @@ __global__ __launch_bounds__(kWaves * 64) void full_mttkrp_kernel(FullArgs a) {
                 }
             }
         }
+        __builtin_amdgcn_sched_barrier(0);  // the tensor loads stay issued together
         __syncthreads();  // the previous tile's Khatri-Rao rows are no longer read
         // ---- Khatri-Rao rows of the tile: factor offsets, then products
         for (int ql = tid; ql < kQT; ql += kWaves * 64) {
             int64_t q = q0 + ql;
             if (ql >= nq) q = q0;  // past the end: any valid column (its row is zeroed)
-            int64_t j = q % J, k = q / J;
+            if (small) {
+                uint32_t j = (uint32_t)q % (uint32_t)J, k = (uint32_t)q / (uint32_t)J;
 #pragma unroll
-            for (int m = 0; m < kMaxOrder; ++m) {
-                if (m >= N) break;
-                int64_t im = 0;
-                if (m < n) {
-                    im = j % a.mi.dims[m];
-                    j /= a.mi.dims[m];
-                } else if (m > n) {
-                    im = k % a.mi.dims[m];
-                    k /= a.mi.dims[m];
+                for (int m = 0; m < kMaxOrder; ++m) {
+                    if (m >= N) break;
+                    uint32_t im = 0;
+                    const uint32_t d = (uint32_t)a.mi.dims[m];
+                    if (m < n) {
+                        im = j % d;
+                        j /= d;
+                    } else if (m > n) {
+                        im = k % d;
+                        k /= d;
+                    }
+                    qoff[ql][m] = (int64_t)im * R;
                 }
-                qoff[ql][m] = im * R;
+            } else {
+                int64_t j = q % J, k = q / J;
+#pragma unroll
+                for (int m = 0; m < kMaxOrder; ++m) {
+                    if (m >= N) break;
+                    int64_t im = 0;
+                    if (m < n) {
+                        im = j % a.mi.dims[m];
+                        j /= a.mi.dims[m];
+                    } else if (m > n) {
+                        im = k % a.mi.dims[m];
+                        k /= a.mi.dims[m];
+                    }
+                    qoff[ql][m] = im * R;
+                }
             }
         }
         __syncthreads();
         for (int e = tid; e < kQT * 16 * CT; e += kWaves * 64) {
             const int ql = e / (16 * CT), r = e - ql * (16 * CT);
-            T z = (T)0;
-            if (ql < nq && r < R) {
-                z = (T)1;
+            // every slot's factor value loaded (a mode past the order or the
+            // skipped mode reads mode 0's or 1's row again, clamped column)
+            // with no branch between the loads, then multiplied in mode order
+            const int rc = min(r, R - 1);
+            T f[kMaxOrder];
 #pragma unroll
-                for (int m = 0; m < kMaxOrder; ++m) {
-                    if (m >= N) break;
-                    if (m != n) z *= ((const T *)a.A.p[m])[qoff[ql][m] + r];
-                }
+            for (int m = 0; m < kMaxOrder; ++m) {
+                const bool take = m < N && m != n;
+                const int m0 = n == 0 ? 1 : 0;  // a participating mode
+                // compile-time indices into the pointer array (a run-time
+                // index would copy it to scratch)
+                const T *Am = (const T *)(take ? a.A.p[m] : (n == 0 ? a.A.p[1] : a.A.p[0]));
+                f[m] = Am[qoff[ql][take ? m : m0] + rc];
             }
-            Zs[ql * LDB + r] = z;
+            T z = (T)1;
+#pragma unroll
+            for (int m = 0; m < kMaxOrder; ++m)
+                if (m < N && m != n) z *= f[m];
+            Zs[ql * LDB + r] = (ql < nq && r < R) ? z : (T)0;
         }
         __syncthreads();
         // ---- products
         if (rw < In) {
             if (IV) {
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
+                auto mfma_u = [&](int u) {
                     const int ql = 4 * u + lk;
 #pragma unroll
                     for (int ct = 0; ct < CT; ++ct) {
@@ -216,6 +299,18 @@ __global__ __launch_bounds__(kWaves * 64) void full_mttkrp_kernel(FullArgs a) {
 #pragma unroll
                         for (int c = 0; c < VE; ++c) acc[ct][c] = fmfma(v[u][c], b, acc[ct][c]);
                     }
+                };
+                const int64_t qn = q0 + kQT;
+                if (VEC && qn < qb) {
+                    const int nqn = (int)min((int64_t)kQT, qb - qn);
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        mfma_u(u);
+                        load_iv(u, qn, nqn);  // the next tile's vector into the register just read
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) mfma_u(u);
                 }
             } else {
 #pragma unroll
@@ -365,10 +460,11 @@ FullPlan plan_full(const ModeInfo &mi, int kind, int32_t R, bool aligned) {
     const int rpw = 16 * ve;
     f.rows_wg = kWaves * rpw;
     f.row_blocks = (int32_t)ceil_div(f.In, f.rows_wg);
-    // enough workgroups to fill the chip several times over, while the
+    // about the workgroups the chip holds at once (two per CU), so the
+    // grid runs in one round and each workgroup walks many tiles, while the
     // partial products stay within about 2% of the tensor's bytes
     const int64_t tiles = ceil_div(f.Q, kQT);
-    int64_t chunks = ceil_div(2048, f.row_blocks);
+    int64_t chunks = ceil_div(512, f.row_blocks);
     const int64_t cap = std::max<int64_t>(1, (f.Q * (int64_t)f.In) / ((int64_t)f.In * R * 50));
     chunks = std::max<int64_t>(1, std::min({chunks, cap, tiles}));
     f.qchunk = ceil_div(tiles, chunks) * kQT;
