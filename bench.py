@@ -607,8 +607,9 @@ def gather_leg(P, synth, torch, dev, reps=10):
     """Throughput of the sampled MTTKRP at the shape of a mode step but with
     enough uniformly drawn samples (many independent draws' worth, one
     launch) that each call moves about 1 GB of fibers: FP32 fibers of 1000
-    (the 1000^3 tensor, mode 0, contiguous) and complex64 fibers of 400 (the
-    mixed 400^3 tensor, mode 0), rank 10.  Useful bytes = S I_n b_X per call;
+    (the 1000^3 tensor, mode 0, contiguous), the same tensor's BF16 copy
+    (twice the samples), and complex64 fibers of 400 (the mixed 400^3
+    tensor, mode 0), rank 10.  Useful bytes = S I_n b_X per call;
     the 1000^3 tensor has 10^6 fibers per mode, so few of the 256,000 draws
     repeat a fiber (the cache cannot serve them)."""
     R = 10
@@ -618,8 +619,13 @@ def gather_leg(P, synth, torch, dev, reps=10):
     prob4 = synth.problem_for(w4)
     print("[bench] generating %s for the gather leg" % w4.name, flush=True)
     X4 = synth.device_tensor(prob4, dev, "f32")
-    cases.append(("f32_1000cube_mode0", P.View(X4, w4.dims), w4.dims, 0, 256000, 4,
-                  [torch.as_tensor(M[:, :R], dtype=torch.float32, device=dev).contiguous() for M in prob4.init], None))
+    A4 = [torch.as_tensor(M[:, :R], dtype=torch.float32, device=dev).contiguous() for M in prob4.init]
+    cases.append(("f32_1000cube_mode0", P.View(X4, w4.dims), w4.dims, 0, 256000, 4, A4, None))
+    # the BF16 form of the same tensor (a mode-0-major BF16 copy): twice the
+    # samples for the same 1.024 GB of fibers, on BF16 MFMA
+    Yb = P.mode_major_copy(P.View(X4, w4.dims), 0, dtype=torch.bfloat16)
+    cases.append(("bf16_1000cube_mode0", P.View(Yb.data, Yb.dims, Yb.strides, dtype=P.BF16), w4.dims, 0, 512000, 2,
+                  A4, None))
     w2 = synth.WORKLOADS["cprand-400cube-f32"]
     prob2 = synth.problem_for(w2)
     X2 = synth.device_tensor(prob2, dev, "f32")
@@ -641,7 +647,7 @@ def gather_leg(P, synth, torch, dev, reps=10):
                      "useful_GBps": gbs, "frac_of_hbm": gbs / HBM_PEAK_GBS}
         print("[bench] gather %s: %.3f ms per call, %.0f GB/s useful (%.2f of HBM)"
               % (name, ms, gbs, gbs / HBM_PEAK_GBS), flush=True)
-    del X4, Xh
+    del X4, Xh, Yb
     torch.cuda.empty_cache()
     return res
 
