@@ -14,6 +14,7 @@
 // Each pass reads and writes 1 real element per element of the tensor.
 #include <math.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -170,6 +171,231 @@ __global__ __launch_bounds__(NT) void dct_pass_kernel(FftPlan fp, const Tin *X, 
     }
 }
 
+// Software-pipelined form for long FP32 tensors (compile-time lengths): a
+// persistent grid walks tiles of 2 TC real fibers, t = blockIdx.x,
+// blockIdx.x + gridDim.x, ...; the 16-byte loads of the next tile are held
+// in registers through the current tile's FFT, as in the CPRAND-MIX passes.
+// FIRST (m = 0, fibers contiguous in X): vectors run along the fiber (4
+// elements of one fiber); otherwise along j (4 neighbouring fibers, which lie
+// in one k because J % 4 == 0).  A tile may straddle k: offsets are per
+// fiber.  Makhoul's reordering is applied on the LDS write, the post-rotation
+// on the store.  Fibers past the end read fiber 0 (zero sign, or output not
+// stored).
+template <int L, int TC, int NT, bool FIRST>
+__global__ __launch_bounds__(NT) void dct_pass_pipe(const float *X, float *Y, int64_t J, int64_t K, ModeInfo xi,
+                                                    const int8_t *signs, const cx<float> *twg, const cx<float> *csg) {
+    constexpr int LDT = TC + 1;
+    constexpr int FC = 2 * TC;                // real fibers per tile
+    constexpr int NV = L * FC / 4;            // float4 per tile
+    constexpr int PF = (NV + NT - 1) / NT;    // float4 per thread
+    static_assert(!FIRST || L % 4 == 0, "vectors along the fiber");
+    __shared__ cx<float> buf[L * LDT];
+    __shared__ cx<float> tw[L];
+    __shared__ cx<float> cs[L];
+    // tile offsets (and FIRST: input offsets and sign products) in three
+    // slots: the slot written for the next tile was last read two iterations
+    // ago, before the previous barrier
+    __shared__ int64_t cout[3][FC];
+    __shared__ int64_t cin[3][FIRST ? FC : 1];
+    __shared__ float csign[3][FIRST ? FC : 1];
+    __shared__ float lsign[FIRST ? L : 1];
+    const int tid = threadIdx.x;
+    const int64_t ncols = J * K;
+    const int64_t ntiles = ceil_div(ncols, FC);
+    const bool small = ncols < (int64_t)INT32_MAX;
+    for (int e = tid; e < L; e += NT) {
+        tw[e] = twg[e];
+        cs[e] = csg[e];
+        if (FIRST) lsign[e] = (float)signs[e];
+    }
+    auto tile_info = [&](int64_t t, int slot) {
+        for (int c = tid; c < FC; c += NT) {
+            const int64_t q = t * FC + c;
+            if (q >= ncols) {
+                cout[slot][c] = 0;
+                if (FIRST) {
+                    cin[slot][c] = 0;
+                    csign[slot][c] = 0.f;
+                }
+                continue;
+            }
+            if (small) {  // 32-bit index arithmetic (the divisions sit before a barrier)
+                const uint32_t j = (uint32_t)q % (uint32_t)J, k = (uint32_t)q / (uint32_t)J;
+                cout[slot][c] = (int64_t)j + J * L * (int64_t)k;
+            } else {
+                const int64_t j = q % J, k = q / J;
+                cout[slot][c] = j + J * L * k;
+            }
+            if (FIRST) {  // m = 0: q runs over modes 1 .. order-1
+                int64_t off = 0;
+                float sg = 1.f;
+                int soff = (int)xi.dims[0];
+                if (small) {
+                    uint32_t r = (uint32_t)q;
+                    for (int mm = 1; mm < xi.order; ++mm) {
+                        const uint32_t d = (uint32_t)xi.dims[mm];
+                        const uint32_t im = r % d;
+                        r /= d;
+                        off += (int64_t)im * xi.strides[mm];
+                        sg *= (float)signs[soff + (int)im];
+                        soff += (int)d;
+                    }
+                } else {
+                    int64_t r = q;
+                    for (int mm = 1; mm < xi.order; ++mm) {
+                        const int64_t im = r % xi.dims[mm];
+                        r /= xi.dims[mm];
+                        off += im * xi.strides[mm];
+                        sg *= (float)signs[soff + im];
+                        soff += (int)xi.dims[mm];
+                    }
+                }
+                cin[slot][c] = off;
+                csign[slot][c] = sg;
+            }
+        }
+    };
+    float4 r[PF];
+    auto issue_loads = [&](int slot) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int e = tid + u * NT;
+            r[u] = float4{0.f, 0.f, 0.f, 0.f};
+            if (e < NV) {
+                if (FIRST) {  // fiber fastest: 4 elements of fiber c
+                    const int c = e % FC, l4 = (e / FC) * 4;
+                    r[u] = *(const float4 *)(X + cin[slot][c] + l4);
+                } else {      // row l: fibers c4 .. c4 + 3
+                    const int l = e / (FC / 4), c4 = (e - l * (FC / 4)) * 4;
+                    r[u] = *(const float4 *)(Y + cout[slot][c4] + J * (int64_t)l);
+                }
+            }
+        }
+    };
+    auto perm = [](int l) { return (l & 1) ? (L - 1 - (l >> 1)) : (l >> 1); };
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    tile_info(t, 0);
+    __syncthreads();
+    issue_loads(0);
+    for (int it = 0; t < ntiles; ++it, t += gridDim.x) {
+        const int cur = it % 3, nxt = (it + 1) % 3;
+        const int nc = (int)min((int64_t)FC, ncols - t * FC);
+        const int64_t tn = t + gridDim.x;
+        if (tn < ntiles) tile_info(tn, nxt);
+        __syncthreads();  // the previous tile's output reads are done; tile_info(tn) is visible
+        // registers (tile t) -> LDS in Makhoul's order: fiber c to the real
+        // (even c) or imaginary (odd c) part of column c / 2
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int e = tid + u * NT;
+            if (e >= NV) continue;
+            const float4 v = r[u];
+            if (FIRST) {
+                const int c = e % FC, l4 = (e / FC) * 4;
+                const float sc = csign[cur][c];
+                float *bf = (float *)buf + (c & 1);
+                const int cc = c >> 1;
+                bf[2 * (perm(l4 + 0) * LDT + cc)] = v.x * sc * lsign[l4 + 0];
+                bf[2 * (perm(l4 + 1) * LDT + cc)] = v.y * sc * lsign[l4 + 1];
+                bf[2 * (perm(l4 + 2) * LDT + cc)] = v.z * sc * lsign[l4 + 2];
+                bf[2 * (perm(l4 + 3) * LDT + cc)] = v.w * sc * lsign[l4 + 3];
+            } else {
+                const int l = e / (FC / 4), c4 = (e - l * (FC / 4)) * 4;
+                const int p = perm(l);
+                buf[p * LDT + (c4 >> 1)] = {v.x, v.y};
+                buf[p * LDT + (c4 >> 1) + 1] = {v.z, v.w};
+            }
+        }
+        // the next tile's loads stay in flight through this tile's FFT
+        if (tn < ntiles) issue_loads(nxt);
+        __syncthreads();
+        fft_ct<float, L, TC, NT, -1>(buf, tw);
+        __syncthreads();
+        // y_c[k] = (s_k / 2)(cos(pi k / 2L) a + sin(pi k / 2L) b), (a, b) from
+        // Z[k] and Z[L - k] of column c / 2 (conjugate-symmetric split)
+        auto out1 = [&](int c, int k) {
+            const int cc = c >> 1, mk = k == 0 ? 0 : L - k;
+            const cx<float> zk = buf[k * LDT + cc], zm = buf[mk * LDT + cc];
+            float a, b;
+            if (c & 1) {
+                a = zk.im + zm.im;
+                b = zm.re - zk.re;
+            } else {
+                a = zk.re + zm.re;
+                b = zk.im - zm.im;
+            }
+            const cx<float> w = cs[k];
+            return 0.5f * (w.re * a + w.im * b);
+        };
+        if (FIRST) {
+            // one k per lane: consecutive lanes read consecutive LDS rows
+            // (no bank conflicts) and write consecutive words of a fiber
+            for (int e = tid; e < FC * L; e += NT) {
+                const int c = e / L, k = e - c * L;
+                if (c < nc) Y[cout[cur][c] + k] = out1(c, k);
+            }
+        } else {
+            for (int e = tid; e < L * (FC / 4); e += NT) {
+                const int k = e / (FC / 4), c4 = (e - k * (FC / 4)) * 4;
+                if (c4 >= nc) continue;
+                *(float4 *)(Y + cout[cur][c4] + J * (int64_t)k) = float4{out1(c4, k), out1(c4 + 1, k),
+                                                                         out1(c4 + 2, k), out1(c4 + 3, k)};
+            }
+        }
+    }
+}
+
+// resident workgroups of a kernel on the current device (cached per call
+// site by the caller)
+template <typename Kern>
+static unsigned resident_blocks(Kern kernel, int nt, unsigned &per_cu) {
+    if (per_cu == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, nt, 0) != hipSuccess || n < 1) n = 1;
+        per_cu = (unsigned)n;
+    }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || cus < 1)
+        cus = 256;
+    return per_cu * (unsigned)cus;
+}
+
+// The pipelined pass when its vector accesses are legal: FIRST needs unit
+// stride along mode 0, 16-byte aligned fiber starts in X and Y and L % 4 ==
+// 0; the other passes need J % 4 == 0 and Y aligned.  Returns false (nothing
+// launched) otherwise.
+template <int L, int TC, int NT>
+static bool launch_dct_pipe(const FftPlan *fp, const void *tab, const ModeInfo &xi, const void *X, void *Y,
+                            bool first, const int8_t *signs, int64_t J, int64_t K, hipStream_t st, hipError_t *err) {
+    const bool ya = (((uintptr_t)Y) & 15) == 0;
+    const int64_t ntiles = ceil_div(J * K, 2 * TC);
+    if (first) {
+        if constexpr (L % 4 == 0) {
+            bool ok = J == 1 && ya && (((uintptr_t)X) & 15) == 0 && xi.strides[0] == 1;
+            for (int mm = 1; mm < xi.order; ++mm) ok = ok && xi.strides[mm] % 4 == 0;
+            if (!ok) return false;
+            static unsigned per_cu = 0;
+            const unsigned np = (unsigned)std::min<int64_t>(ntiles, resident_blocks(dct_pass_pipe<L, TC, NT, true>,
+                                                                                      NT, per_cu));
+            hipLaunchKernelGGL((dct_pass_pipe<L, TC, NT, true>), dim3(np), dim3(NT), 0, st, (const float *)X,
+                               (float *)Y, J, K, xi, signs, (const cx<float> *)fp->tw, (const cx<float> *)tab);
+            *err = hipGetLastError();
+            return true;
+        }
+        return false;
+    }
+    if (J % 4 != 0 || !ya) return false;
+    static unsigned per_cu = 0;
+    const unsigned np = (unsigned)std::min<int64_t>(ntiles, resident_blocks(dct_pass_pipe<L, TC, NT, false>, NT,
+                                                                              per_cu));
+    hipLaunchKernelGGL((dct_pass_pipe<L, TC, NT, false>), dim3(np), dim3(NT), 0, st, (const float *)nullptr,
+                       (float *)Y, J, K, xi, signs, (const cx<float> *)fp->tw, (const cx<float> *)tab);
+    *err = hipGetLastError();
+    return true;
+}
+
 template <typename T, typename Tin, int LC, int TC, int NT>
 static hipError_t launch_dct_tiles(const FftPlan *fp, const void *tab, const ModeInfo &xi, const void *X, void *Y,
                                      int m, bool first, const int8_t *signs, int64_t J, int64_t K, hipStream_t st) {
@@ -217,10 +443,16 @@ hipError_t launch_dct_pass(const ModeInfo &xi, const void *X, int xkind, void *Y
     }
     if (first && xkind == K_F64) return launch_dct_generic<float, double>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
     if (first && xkind != K_F32) return hipErrorInvalidValue;
-    switch (fp->L) {  // compile-time schedules for the common lengths
-        case 60: return launch_dct_tiles<float, float, 60, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
-        case 150: return launch_dct_tiles<float, float, 150, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
-        case 400: return launch_dct_tiles<float, float, 400, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+    switch (fp->L) {  // compile-time schedules for the common lengths (pipelined when the layout allows)
+        case 60:
+            if (launch_dct_pipe<60, 16, 512>(fp, tab, xi, X, Y, first, signs, J, K, st, &e)) return e;
+            return launch_dct_tiles<float, float, 60, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+        case 150:
+            if (launch_dct_pipe<150, 16, 512>(fp, tab, xi, X, Y, first, signs, J, K, st, &e)) return e;
+            return launch_dct_tiles<float, float, 150, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+        case 400:
+            if (launch_dct_pipe<400, 16, 1024>(fp, tab, xi, X, Y, first, signs, J, K, st, &e)) return e;
+            return launch_dct_tiles<float, float, 400, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
         default: return launch_dct_generic<float, float>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
     }
 }
