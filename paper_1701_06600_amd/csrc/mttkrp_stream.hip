@@ -39,7 +39,7 @@ __host__ __device__ constexpr int stream_gw() {
 }
 
 template <typename T, bool CPLX, int CT, bool WEIGHTED>
-__global__ __launch_bounds__(256) void gather_stream(KArgs a) {
+__device__ __forceinline__ void gather_stream_body(const KArgs &a) {
     typedef Geo<T, CPLX> G;
     typedef typename AccT<T>::type Acc;
     constexpr int GW = stream_gw<T, CPLX, CT>();
@@ -291,6 +291,25 @@ __global__ __launch_bounds__(256) void gather_stream(KArgs a) {
 }
 
 template <typename T, bool CPLX, int CT, bool WEIGHTED>
+__global__ __launch_bounds__(256) void gather_stream(KArgs a) {
+    gather_stream_body<T, CPLX, CT, WEIGHTED>(a);
+}
+
+// The same with the registers held to four waves per SIMD: complex64 at
+// R <= 16 then runs at occupancy 4 without spilling (its matrix work per
+// byte is twice the real case's, and the extra waves hide it).
+template <typename T, bool CPLX, int CT, bool WEIGHTED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gather_stream_o4(KArgs a) {
+    gather_stream_body<T, CPLX, CT, WEIGHTED>(a);
+}
+
+// the form a launch uses
+template <typename T, bool CPLX, int CT>
+constexpr bool stream_o4() {
+    return CPLX && sizeof(T) == 4 && CT <= 2;
+}
+
+template <typename T, bool CPLX, int CT, bool WEIGHTED>
 static int stream_capacity(size_t lds) {
     // workgroups of this instance the chip holds at once, per device
     static std::mutex mu;
@@ -300,8 +319,12 @@ static int stream_capacity(size_t lds) {
     std::lock_guard<std::mutex> lk(mu);
     if (cap[dev] == 0) {
         int nb = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gather_stream<T, CPLX, CT, WEIGHTED>, 256, lds) !=
-                hipSuccess ||
+        hipError_t qe;
+        if constexpr (stream_o4<T, CPLX, CT>())
+            qe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gather_stream_o4<T, CPLX, CT, WEIGHTED>, 256, lds);
+        else
+            qe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gather_stream<T, CPLX, CT, WEIGHTED>, 256, lds);
+        if (qe != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || nb < 1 ||
             cus < 1) {
             (void)hipGetLastError();
@@ -348,7 +371,9 @@ int stream_cap(int kind, int ct, size_t lds) {
 template <typename T, bool CPLX, int CT>
 static hipError_t launch_stream_ct(const GatherPlan &gp, const KArgs &k, bool weighted, hipStream_t st) {
     dim3 grid(gp.row_blocks, gp.chunks), block(64 * gp.waves);
-    if (weighted && !CPLX)
+    if constexpr (stream_o4<T, CPLX, CT>())
+        hipLaunchKernelGGL((gather_stream_o4<T, CPLX, CT, false>), grid, block, gp.lds_bytes, st, k);
+    else if (weighted && !CPLX)
         hipLaunchKernelGGL((gather_stream<T, CPLX, CT, true>), grid, block, gp.lds_bytes, st, k);
     else
         hipLaunchKernelGGL((gather_stream<T, CPLX, CT, false>), grid, block, gp.lds_bytes, st, k);
