@@ -28,10 +28,10 @@ __global__ __launch_bounds__(256) void gather_contract(KArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-GatherPlan plan_gather_bf16(int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks);
+GatherPlan plan_gather_bf16(int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks, int order);
 
 GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_ok, int max_chunks, int order) {
-    if (kind == K_BF16) return plan_gather_bf16(R, S, In, contig_ok, max_chunks);
+    if (kind == K_BF16) return plan_gather_bf16(R, S, In, contig_ok, max_chunks, order);
     GatherPlan g{};
     g.kind = kind;
     g.R = R;

@@ -116,3 +116,39 @@ def test_rank_above_stream_limit_matches_oracle():
     Wr, Vr = OC.sampled_normal_blocks(_r32(X), OP.sample_indices(dims, 0, S, 51, 0), [_r32(M) for M in A], 0)
     close(W.cpu().numpy(), Wr, 1e-5, "W")
     close(V.cpu().numpy(), Vr, 1e-5, "V")
+
+
+@pytest.mark.parametrize("dims,R,S,modes,weighted", [
+    ((1000, 40, 30), 10, 9001, (0, 1, 2), False),  # mode 0: 8 row groups of 128, two per wave, the last of 104
+                                                   # rows; mode 1: one group of 40 rows; mode 2: I_n % 8 != 0
+    ((1288, 30, 20), 20, 6000, (0,), False),       # three row blocks, the last ending in a group of 8 rows;
+                                                   # four Gram tiles
+    ((512, 40, 30), 12, 5000, (0,), True),         # importance weights: V = bf16(w z)^T bf16(z)
+])
+def test_stream_bf16_matches_bf16_oracle(dims, R, S, modes, weighted):
+    """BF16 fibers on long sample sets (the register-transposed streaming
+    form where I_n % 8 == 0) against the oracle of the BF16 product: the same
+    roundings, sums in FP64, so only the FP32 accumulation remains."""
+    from oracle import precision as OR
+    rng = np.random.default_rng(26)
+    X = rng.standard_normal(dims).astype(np.float32)
+    A = [rng.standard_normal((I, R)).astype(np.float32) for I in dims]
+    Xv = view_of(X, torch.float32)
+    Ad = factors_dev(A, torch.float32)
+    for n in modes:
+        Y = P.mode_major_copy(Xv, n, dtype=torch.bfloat16)
+        Yv = P.View(Y.data, Y.dims, Y.strides, dtype=P.BF16)
+        if weighted:
+            qs = [OQ.quantize(rng.dirichlet(np.ones(I)), 0.2) for I in dims]
+            cdfs = [dev(OQ.cdf(q).astype(np.uint64)) for q in qs]
+            idx, w = P.cprand_sample(dims, n, S, 5, 1, cdf=cdfs)
+            ridx, rw = OQ.importance_indices(dims, n, S, 5, 1, qs)
+        else:
+            idx, w = P.cprand_sample(dims, n, S, 33, n)
+            ridx, rw = OP.sample_indices(dims, n, S, 33, n), None
+        W, V = P.cprand_mttkrp_sampled(Yv, n, Ad, R, S, idx, w=w)
+        Wr, Vr = OR.bf16_normal_blocks(X, ridx, A, n, rw)
+        close(W.cpu().numpy(), Wr, 1e-5, "BF16 W mode %d" % n)
+        close(V.cpu().numpy(), Vr, 1e-12, "BF16 V mode %d" % n)
+        W2, V2 = P.cprand_mttkrp_sampled(Yv, n, Ad, R, S, idx, w=w)
+        assert torch.equal(W, W2) and torch.equal(V, V2)
