@@ -101,7 +101,8 @@ GatherPlan plan_gather(int kind, int32_t R, int32_t S, int64_t In, bool contig_o
     g.kc = kc;
     g.chunks = (int)ceil_div(S, kc);
     g.contig = contig_ok;
-    g.lds_bytes = lds_for(kc);
+    // R <= 16: room for the four partial Gram tiles summed at the end
+    g.lds_bytes = std::max(lds_for(kc), (size_t)(R <= 16 ? 4 * 64 * 4 * 8 : 0));
     return g;
 }
 

@@ -443,9 +443,15 @@ __device__ __forceinline__ void gather_chunk(const KArgs &a, unsigned char *lds,
     T *Bim = Bre + (size_t)KC * LDB;                       // complex only
     T *Zr = CPLX ? Bre : (WEIGHTED ? Bre + (size_t)KC * LDB : Bre);  // raw z (real)
 
-    // ---- (1) indices, weights and fiber offsets
-    const uint64_t tt = a.t_dev ? *a.t_dev : a.t;
-    chunk_indices(a, tt, s0, ns, KC, s_base, s_w, s_idx, tid);
+    // ---- (1) indices, weights and fiber offsets.  Given samples never read
+    // the device-side iteration counter: its load would be one more round
+    // trip ahead of the index loads.
+    if (a.idx) {  // uniform
+        chunk_indices_given(a, s0, ns, KC, s_base, s_w, s_idx, tid);
+    } else {
+        const uint64_t tt = a.t_dev ? *a.t_dev : a.t;
+        chunk_indices(a, tt, s0, ns, KC, s_base, s_w, s_idx, tid);
+    }
     // zero the B operand tiles (padding columns and samples stay zero)
     {
         const int words = (int)(((size_t)KC * LDB * sizeof(T) * ((CPLX || WEIGHTED) ? 2 : 1)) / 4);
@@ -454,17 +460,21 @@ __device__ __forceinline__ void gather_chunk(const KArgs &a, unsigned char *lds,
     }
     __syncthreads();
 
-    // ---- fiber loads (phase 4 below): the first batch of this wave's first
-    // row group is issued now, so its latency overlaps the Khatri-Rao loads
+    // ---- fiber loads (phase 4 below): the first two batches of this wave's
+    // first row group are issued now, so their latency overlaps the
+    // Khatri-Rao loads (a chunk of up to 8 kUnroll samples then meets no
+    // fiber round trip after them)
     const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
     const int In = a.In;
     const int row_end = min(In, (int)(blockIdx.x + 1) * a.rows_wg);
     const T *xp = (const T *)a.X;
     const int64_t sn = a.mi.strides[n];
-    T v[kUnroll][G::NV];
+    T v[kUnroll][G::NV], v2[kUnroll][G::NV];
     const bool fast = In % G::VE == 0;
     const int rb0 = blockIdx.x * a.rows_wg + wv * G::RPW;
-    if (rb0 < row_end) load_fibers<T, CPLX, CONTIG>(v, xp, s_base, ns, 0, rb0 + G::VE * li, lk, In, sn, fast);
+    const int npre = rb0 < row_end ? (ns > 4 * kUnroll ? 2 : 1) : 0;  // uniform per wave
+    if (npre > 0) load_fibers<T, CPLX, CONTIG>(v, xp, s_base, ns, 0, rb0 + G::VE * li, lk, In, sn, fast);
+    if (npre > 1) load_fibers<T, CPLX, CONTIG>(v2, xp, s_base, ns, 4 * kUnroll, rb0 + G::VE * li, lk, In, sn, fast);
 
     // ---- (2) sampled Khatri-Rao rows
     chunk_krp<T, CPLX, WEIGHTED>(a, ns, LDB, s_idx, s_w, Bre, Bim, Zr, tid);
@@ -474,38 +484,26 @@ __device__ __forceinline__ void gather_chunk(const KArgs &a, unsigned char *lds,
     // zr zr^T + zi zi^T) over the chunk's samples k, FP64, fixed order.
     // No barrier: waves without Gram work go on to the fiber products.
     const int nrb = gram_nrb, rb = gram_rb;
+    // R <= 16: the one 16 x 16 tile on FP64 MFMA in row block 0, wave w
+    // taking the k-steps w, w + 4, ...; the four partial tiles are summed in
+    // wave order once the fiber products are done (below).  Lane (li, lk)
+    // feeds A(r = li, k) and B(k, q = li) and holds V(lk + 4 v, li).
+    v4d gacc = {0.0, 0.0, 0.0, 0.0};
     if (R <= 16) {
-        // one output tile: entries p = (r, q) dealt to the chunk's row blocks
-        // (p mod row blocks); tpp lanes share an entry, each summing every
-        // tpp-th sample, and a shuffle tree over the tpp lanes closes the sum
-        const int nmine = (R * R - rb + nrb - 1) / nrb;  // entries of this block
-        int tpp = 1;
-        while (tpp < 16 && 2 * tpp * nmine <= nthr) tpp *= 2;
-        const int per = nthr / tpp;  // entries per pass
-        for (int base = 0; base < nmine; base += per) {
-            const int k = base + tid / tpp, part = tid & (tpp - 1);
-            const int p = rb + nrb * k;
-            const int r = p / R, q = p - (p / R) * R;
-            const bool act = k < nmine && q >= r;
-            double acc = 0.0;
-            if (act) {
-                for (int sl = part; sl < ns; sl += tpp) {
-                    if (!CPLX) {
-                        double t = (double)Zr[sl * LDB + r] * (double)Zr[sl * LDB + q];
-                        if (WEIGHTED) t *= s_w[sl];
-                        acc += t;
-                    } else {
-                        acc += (double)Bre[sl * LDB + r] * (double)Bre[sl * LDB + q] +
-                               (double)Bim[sl * LDB + r] * (double)Bim[sl * LDB + q];
-                    }
+        if (rb == 0) {  // uniform per workgroup
+            const bool rin = li < R;
+            for (int kk = wv; kk < (ns + 3) / 4; kk += 4) {  // rows past ns are zero
+                const int sl = 4 * kk + lk;
+                if (!CPLX) {
+                    double av = rin ? (double)Zr[sl * LDB + li] : 0.0;
+                    if (WEIGHTED) av *= s_w[sl];
+                    gacc = mfma16(av, rin ? (double)Zr[sl * LDB + li] : 0.0, gacc);
+                } else {
+                    const double zr = rin ? (double)Bre[sl * LDB + li] : 0.0;
+                    const double zi = rin ? (double)Bim[sl * LDB + li] : 0.0;
+                    gacc = mfma16(zr, zr, gacc);
+                    gacc = mfma16(zi, zi, gacc);
                 }
-            }
-#pragma unroll
-            for (int o = 8; o > 0; o >>= 1)
-                if (o < tpp) acc += __shfl_xor(acc, o, 64);  // uniform: tpp is the same in every lane
-            if (act && part == 0) {
-                vp[r * R + q] = acc;
-                vp[q * R + r] = acc;
             }
         }
     } else {
@@ -556,7 +554,7 @@ __device__ __forceinline__ void gather_chunk(const KArgs &a, unsigned char *lds,
     // time (a workgroup covers rows_wg rows: one group per wave for short
     // sample chunks, whole fibers for long ones)
     T *wp = (T *)a.wpart + (size_t)chunk * a.ncols * In;
-    bool preloaded = rb0 < row_end;
+    int inreg = npre;  // batches of this row group already in registers
     for (int rowbase = rb0; rowbase < row_end; rowbase += (int)(blockDim.x >> 6) * G::RPW) {
     const int row0 = rowbase + G::VE * li;
 
@@ -567,8 +565,15 @@ __device__ __forceinline__ void gather_chunk(const KArgs &a, unsigned char *lds,
         for (int c = 0; c < G::VE; ++c) acc[ct][c] = Acc{0, 0, 0, 0};
 
     for (int ks = 0; ks < ns; ks += 4 * kUnroll) {
-        if (!preloaded) load_fibers<T, CPLX, CONTIG>(v, xp, s_base, ns, ks, row0, lk, In, sn, fast);
-        preloaded = false;
+        const int b = ks / (4 * kUnroll);
+        if (b >= inreg) {
+            load_fibers<T, CPLX, CONTIG>(v, xp, s_base, ns, ks, row0, lk, In, sn, fast);
+        } else if (b == 1) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+                for (int e = 0; e < G::NV; ++e) v[u][e] = v2[u][e];
+        }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             if (ks + 4 * u >= ns) break;  // uniform: the rest of this pass is past the chunk
@@ -599,7 +604,32 @@ __device__ __forceinline__ void gather_chunk(const KArgs &a, unsigned char *lds,
             store_group<T, G::VE>(wp + (size_t)col * In, acc[ct], rowbase, row_end, lk,
                                   In % (sizeof(T) == 4 && G::VE == 4 ? 4 : 2) == 0);
     }
+    inreg = 0;
     }  // row groups
+
+    if (R <= 16 && rb == 0) {  // uniform per workgroup
+        // the four waves' partial Gram tiles, summed in wave order through
+        // LDS (the chunk's tiles are no longer read), then V(r, q) for
+        // q >= r, mirrored so that V is exactly symmetric
+        __syncthreads();
+        double *gt = (double *)lds;
+#pragma unroll
+        for (int v4 = 0; v4 < 4; ++v4) gt[(wv * 64 + l) * 4 + v4] = gacc[v4];
+        __syncthreads();
+        if (wv == 0) {
+#pragma unroll
+            for (int v4 = 0; v4 < 4; ++v4) {
+                double t = gt[l * 4 + v4];
+#pragma unroll
+                for (int w2 = 1; w2 < 4; ++w2) t += gt[(w2 * 64 + l) * 4 + v4];
+                const int r = lk + 4 * v4, q = li;
+                if (r < R && q < R && q >= r) {
+                    vp[r * R + q] = t;
+                    vp[q * R + r] = t;
+                }
+            }
+        }
+    }
 }
 
 // Streaming form (mttkrp_stream.hip): row groups per wave for a plan (0 when
