@@ -55,7 +55,9 @@ __global__ __launch_bounds__(256) void gather_contract_bf16(BfArgs a) {
     uint16_t *Zt = (uint16_t *)(zf + (size_t)KC * R);                              // 16*CT x ldz
     uint16_t *At = Zt + (size_t)16 * CT * ldz;                                      // kBfRows x lda
 
-    const uint64_t tt = a.t_dev ? *a.t_dev : a.t;
+    // given samples never read the device-side iteration counter (its load
+    // would be one more round trip ahead of the index loads)
+    const uint64_t tt = a.idx ? 0 : (a.t_dev ? *a.t_dev : a.t);
     for (int sl = tid; sl < KC; sl += blockDim.x) {
         int64_t row[kMaxOrder];
         double wv = 0.0;
