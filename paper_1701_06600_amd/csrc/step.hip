@@ -49,7 +49,10 @@ struct Vec16<double> {
 __device__ inline float vget(const float4 &v, int u) { return u == 0 ? v.x : u == 1 ? v.y : u == 2 ? v.z : v.w; }
 __device__ inline double vget(const double2 &v, int u) { return u == 0 ? v.x : v.y; }
 
-template <typename T>
+// MIX: the mixed-domain step, a compile-time parameter so that each
+// instance holds only its own path (the kernel runs as one workgroup on one
+// CU, so its code is fetched cold at every launch: less of it is faster)
+template <typename T, bool MIX>
 __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int In = a.In, R = a.R, ld = R + 1;
@@ -120,7 +123,7 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
                 vw[q] = (i < R && j < R) ? acc : 0.0;
             }
         }
-        if (!a.mix) __syncthreads();  // uniform condition
+        if (!MIX) __syncthreads();
     }
     // The product partials: all threads, or (R <= 16) waves 1.. while wave 0
     // inverts V.
@@ -128,7 +131,7 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
     if (yt >= 0) {
         constexpr int VL = 16 / sizeof(T);  // values per 16-byte load
         typedef typename Vec16<T>::type V16;
-        if (!a.mix && a.wsi == 1 && In % VL == 0 && a.wsr % VL == 0 && a.wps % VL == 0) {
+        if (!MIX && a.wsi == 1 && In % VL == 0 && a.wsr % VL == 0 && a.wps % VL == 0) {
             // (i .. i+VL-1, r) of every partial in one 16-byte load each
             const T *w = (const T *)a.W;
             const int ng = R * (In / VL);
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
                     Wd[(i0 + u) * R + r] = acc;
                 }
             }
-        } else if (a.mix && In % VL == 0) {
+        } else if (MIX && In % VL == 0) {
             // real and imaginary rows of column c, VL consecutive l per load; two
             // groups per thread per pass, all their loads in flight together
             const T *y = (const T *)a.W;
@@ -185,7 +188,7 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
                     }
                 }
             }
-        } else if (!a.mix) {
+        } else if (!MIX) {
             const T *w = (const T *)a.W;
             for (int e0 = yt; e0 < In * R; e0 += 2 * ys) {
                 T v[2][kMaxParts];
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
         failed = spd_inverse(B1, B2, B3, tmp, R, ld, cs, pairs);
     }
     if (tid == 0 && a.info && failed) *a.info = CPRAND_W_PINV;
-    if (a.mix) {
+    if (MIX) {
         // A-hat (unnormalised) = Y_s V^{-1} with Y_s = (Y + P conj Y) / 2:
         // rows k and I_n - k of Y_s are conjugates (rows 0 and I_n / 2 pair
         // with themselves), so one thread takes the pair, reads both rows of
@@ -466,10 +469,14 @@ hipError_t launch_step_finish(const StepArgs &a, bool dbl, hipStream_t st) {
     if (a.Wref && (!a.vref || a.vrefparts < 1)) return hipErrorInvalidValue;
     if (a.mix && !a.Ahat) return hipErrorInvalidValue;
     const size_t lds = step_finish_lds(a.In, a.R, a.mix);
-    if (dbl)
-        hipLaunchKernelGGL(step_finish_kernel<double>, dim3(1), dim3(kStepThreads), lds, st, a);
+    if (dbl && a.mix)
+        hipLaunchKernelGGL((step_finish_kernel<double, true>), dim3(1), dim3(kStepThreads), lds, st, a);
+    else if (dbl)
+        hipLaunchKernelGGL((step_finish_kernel<double, false>), dim3(1), dim3(kStepThreads), lds, st, a);
+    else if (a.mix)
+        hipLaunchKernelGGL((step_finish_kernel<float, true>), dim3(1), dim3(kStepThreads), lds, st, a);
     else
-        hipLaunchKernelGGL(step_finish_kernel<float>, dim3(1), dim3(kStepThreads), lds, st, a);
+        hipLaunchKernelGGL((step_finish_kernel<float, false>), dim3(1), dim3(kStepThreads), lds, st, a);
     return hipGetLastError();
 }
 
