@@ -849,12 +849,20 @@ int cprand_plan_run(cprand_plan *p, const cprand_tensor *X, void *const *A_inout
             // initial factors with it, then iterate on the mixed tensor
             e = launch_signs(xi, p->o.seed, p->signs, st);
             for (int m = 0; m < N && e == hipSuccess; ++m) {
+                MixExtras ex{};
+                if (m == 0) ex.normsq_part = p->normpart;  // ||X|| folded into the first pass
                 e = hipEventRecord(tev[2 + 2 * m], st);
                 if (e == hipSuccess)
                     e = launch_dct_pass(m == 0 ? xi : xit_i, X->data, p->xkind, p->xdct, p->dbl, m, m == 0, p->signs,
-                                        st);
+                                        st, m == 0 ? &ex : nullptr);
                 if (e == hipSuccess) e = hipEventRecord(tev[3 + 2 * m], st);
                 timed_mix[m] = e == hipSuccess;
+                if (e == hipSuccess && m == 0 && ex.nparts > 0) {
+                    e = hipEventRecord(tev[0], st);
+                    if (e == hipSuccess) e = launch_sqrt_sum(p->normpart, ex.nparts, p->normX, st);
+                    if (e == hipSuccess) e = hipEventRecord(tev[1], st);
+                    norm_done = e == hipSuccess;
+                }
             }
             for (int m = 1; m < N && e == hipSuccess; ++m)
                 e = launch_factor_dct((int32_t)p->dims[m], R, A_inout[m], p->signs + p->seg_off[m], p->fac[m], p->dbl,

@@ -530,11 +530,15 @@ int cprand_mix_dct(const cprand_tensor *X, uint64_t seed, const cprand_tensor *X
     hipStream_t st = (hipStream_t)stream;
     const ModeInfo xi = mode_info(X, 0), hi = mode_info(Xhat, 0);
     hipError_t e = launch_signs(xi, seed, signs, st);
+    // ||X|| from the first pass when its kernel supports it, else its own pass
+    MixExtras ex{};
+    ex.normsq_part = (double *)workspace;
     for (int m = 0; m < X->order && e == hipSuccess; ++m)
-        e = launch_dct_pass(m == 0 ? xi : hi, X->data, xk, Xhat->data, dbl, m, m == 0, signs, st);
+        e = launch_dct_pass(m == 0 ? xi : hi, X->data, xk, Xhat->data, dbl, m, m == 0, signs, st,
+                            m == 0 ? &ex : nullptr);
     if (e == hipErrorInvalidValue) return set_error(CPRAND_EUNSUPPORTED, "a mode is too long for the DCT tile");
-    int32_t np = 0;
-    if (e == hipSuccess) e = launch_normsq_partial(xi, X->data, xk, (double *)workspace, &np, st);
+    int32_t np = ex.nparts;
+    if (e == hipSuccess && np == 0) e = launch_normsq_partial(xi, X->data, xk, (double *)workspace, &np, st);
     if (e == hipSuccess) e = launch_sqrt_sum((double *)workspace, np, normX_out, st);
     return e == hipSuccess ? CPRAND_OK : hip_fail(e, "cprand_mix_dct");
 }

@@ -183,7 +183,8 @@ __global__ __launch_bounds__(NT) void dct_pass_kernel(FftPlan fp, const Tin *X, 
 // stored).
 template <int L, int TC, int NT, bool FIRST>
 __global__ __launch_bounds__(NT) void dct_pass_pipe(const float *X, float *Y, int64_t J, int64_t K, ModeInfo xi,
-                                                    const int8_t *signs, const cx<float> *twg, const cx<float> *csg) {
+                                                    const int8_t *signs, const cx<float> *twg, const cx<float> *csg,
+                                                    double *normsq_part) {
     constexpr int LDT = TC + 1;
     constexpr int FC = 2 * TC;                // real fibers per tile
     constexpr int NV = L * FC / 4;            // float4 per tile
@@ -262,8 +263,8 @@ __global__ __launch_bounds__(NT) void dct_pass_pipe(const float *X, float *Y, in
             const int e = tid + u * NT;
             r[u] = float4{0.f, 0.f, 0.f, 0.f};
             if (e < NV) {
-                if (FIRST) {  // fiber fastest: 4 elements of fiber c
-                    const int c = e % FC, l4 = (e / FC) * 4;
+                if (FIRST) {  // along the fiber: 4 elements of fiber c, a wave reading 1 KB runs
+                    const int c = e / (L / 4), l4 = (e - c * (L / 4)) * 4;
                     r[u] = *(const float4 *)(X + cin[slot][c] + l4);
                 } else {      // row l: fibers c4 .. c4 + 3
                     const int l = e / (FC / 4), c4 = (e - l * (FC / 4)) * 4;
@@ -274,7 +275,11 @@ __global__ __launch_bounds__(NT) void dct_pass_pipe(const float *X, float *Y, in
     };
     auto perm = [](int l) { return (l & 1) ? (L - 1 - (l >> 1)) : (l >> 1); };
     int64_t t = blockIdx.x;
-    if (t >= ntiles) return;
+    if (t >= ntiles) {
+        if (FIRST && normsq_part && tid == 0) normsq_part[blockIdx.x] = 0.0;
+        return;
+    }
+    double nacc = 0.0;  // FIRST: sum of squares of the raw input (signs do not change it)
     tile_info(t, 0);
     __syncthreads();
     issue_loads(0);
@@ -292,8 +297,10 @@ __global__ __launch_bounds__(NT) void dct_pass_pipe(const float *X, float *Y, in
             if (e >= NV) continue;
             const float4 v = r[u];
             if (FIRST) {
-                const int c = e % FC, l4 = (e / FC) * 4;
+                const int c = e / (L / 4), l4 = (e - c * (L / 4)) * 4;
                 const float sc = csign[cur][c];
+                // fibers past the end read fiber 0 (their sign is zero)
+                if (c < nc) nacc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
                 float *bf = (float *)buf + (c & 1);
                 const int cc = c >> 1;
                 bf[2 * (perm(l4 + 0) * LDT + cc)] = v.x * sc * lsign[l4 + 0];
@@ -344,6 +351,11 @@ __global__ __launch_bounds__(NT) void dct_pass_pipe(const float *X, float *Y, in
             }
         }
     }
+    if (FIRST && normsq_part) {
+        __shared__ double sh[NT / kWave];
+        nacc = block_sum<NT>(nacc, sh);
+        if (tid == 0) normsq_part[blockIdx.x] = nacc;
+    }
 }
 
 // resident workgroups of a kernel on the current device (cached per call
@@ -368,7 +380,8 @@ static unsigned resident_blocks(Kern kernel, int nt, unsigned &per_cu) {
 // launched) otherwise.
 template <int L, int TC, int NT>
 static bool launch_dct_pipe(const FftPlan *fp, const void *tab, const ModeInfo &xi, const void *X, void *Y,
-                            bool first, const int8_t *signs, int64_t J, int64_t K, hipStream_t st, hipError_t *err) {
+                            bool first, const int8_t *signs, int64_t J, int64_t K, hipStream_t st, hipError_t *err,
+                            MixExtras *ex) {
     const bool ya = (((uintptr_t)Y) & 15) == 0;
     const int64_t ntiles = ceil_div(J * K, 2 * TC);
     if (first) {
@@ -379,8 +392,10 @@ static bool launch_dct_pipe(const FftPlan *fp, const void *tab, const ModeInfo &
             static unsigned per_cu = 0;
             const unsigned np = (unsigned)std::min<int64_t>(ntiles, resident_blocks(dct_pass_pipe<L, TC, NT, true>,
                                                                                       NT, per_cu));
+            double *nsp = (ex && np <= 4096) ? ex->normsq_part : nullptr;  // partial buffer: 4096 doubles
             hipLaunchKernelGGL((dct_pass_pipe<L, TC, NT, true>), dim3(np), dim3(NT), 0, st, (const float *)X,
-                               (float *)Y, J, K, xi, signs, (const cx<float> *)fp->tw, (const cx<float> *)tab);
+                               (float *)Y, J, K, xi, signs, (const cx<float> *)fp->tw, (const cx<float> *)tab, nsp);
+            if (nsp) ex->nparts = (int32_t)np;
             *err = hipGetLastError();
             return true;
         }
@@ -391,7 +406,8 @@ static bool launch_dct_pipe(const FftPlan *fp, const void *tab, const ModeInfo &
     const unsigned np = (unsigned)std::min<int64_t>(ntiles, resident_blocks(dct_pass_pipe<L, TC, NT, false>, NT,
                                                                               per_cu));
     hipLaunchKernelGGL((dct_pass_pipe<L, TC, NT, false>), dim3(np), dim3(NT), 0, st, (const float *)nullptr,
-                       (float *)Y, J, K, xi, signs, (const cx<float> *)fp->tw, (const cx<float> *)tab);
+                       (float *)Y, J, K, xi, signs, (const cx<float> *)fp->tw, (const cx<float> *)tab,
+                       (double *)nullptr);
     *err = hipGetLastError();
     return true;
 }
@@ -427,7 +443,8 @@ static hipError_t launch_dct_generic(const FftPlan *fp, const void *tab, const M
 }
 
 hipError_t launch_dct_pass(const ModeInfo &xi, const void *X, int xkind, void *Y, bool dbl, int32_t m, bool first,
-                           const int8_t *signs, hipStream_t st) {
+                           const int8_t *signs, hipStream_t st, MixExtras *ex) {
+    if (ex) ex->nparts = 0;
     if (first && m != 0) return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
     const FftPlan *fp = fft_plan_get(xi.dims[m], dbl, &e);
@@ -445,13 +462,13 @@ hipError_t launch_dct_pass(const ModeInfo &xi, const void *X, int xkind, void *Y
     if (first && xkind != K_F32) return hipErrorInvalidValue;
     switch (fp->L) {  // compile-time schedules for the common lengths (pipelined when the layout allows)
         case 60:
-            if (launch_dct_pipe<60, 16, 512>(fp, tab, xi, X, Y, first, signs, J, K, st, &e)) return e;
+            if (launch_dct_pipe<60, 16, 512>(fp, tab, xi, X, Y, first, signs, J, K, st, &e, first ? ex : nullptr)) return e;
             return launch_dct_tiles<float, float, 60, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
         case 150:
-            if (launch_dct_pipe<150, 16, 512>(fp, tab, xi, X, Y, first, signs, J, K, st, &e)) return e;
+            if (launch_dct_pipe<150, 16, 512>(fp, tab, xi, X, Y, first, signs, J, K, st, &e, first ? ex : nullptr)) return e;
             return launch_dct_tiles<float, float, 150, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
         case 400:
-            if (launch_dct_pipe<400, 16, 1024>(fp, tab, xi, X, Y, first, signs, J, K, st, &e)) return e;
+            if (launch_dct_pipe<400, 16, 1024>(fp, tab, xi, X, Y, first, signs, J, K, st, &e, first ? ex : nullptr)) return e;
             return launch_dct_tiles<float, float, 400, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
         default: return launch_dct_generic<float, float>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
     }

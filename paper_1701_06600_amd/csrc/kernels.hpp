@@ -153,9 +153,11 @@ hipError_t launch_fit_exact(const double *W, const void *An, bool dbl, int32_t I
 // (m = 0 only): read X (kind xkind, any strides), apply every mode's signs and
 // write the column-major real tensor Y (double when dbl, else float);
 // otherwise transform Y in place.  hipErrorInvalidValue when the length is
-// not {2,3,5,7}-smooth or its tile does not fit in LDS.
+// not {2,3,5,7}-smooth or its tile does not fit in LDS.  ex (first pass):
+// per-block partial sums of ||X||^2 into ex->normsq_part when the pass's
+// kernel supports it (ex->nparts partials written, else 0).
 hipError_t launch_dct_pass(const ModeInfo &xi, const void *X, int xkind, void *Y, bool dbl, int32_t m, bool first,
-                           const int8_t *signs, hipStream_t st);
+                           const int8_t *signs, hipStream_t st, MixExtras *ex = nullptr);
 // A-hat = C D A (inverse: A = D C^T A-hat) for one I x R row-major factor; in != out.
 hipError_t launch_factor_dct(int32_t I, int32_t R, const void *in, const int8_t *sign, void *out, bool dbl,
                              bool inverse, hipStream_t st);

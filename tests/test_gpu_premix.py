@@ -23,6 +23,8 @@ SHAPES = [
     (50, 50, 50),      # generic lengths, even fiber count
     (60, 7, 9, 5),     # compile-time 60 as mode 0, odd lengths after it
     (400, 20, 3),      # compile-time 400, first pass
+    (60, 7, 5),        # compile-time 60 and 150 first passes (norm folded in), ragged last tile
+    (150, 6, 6),
     (3, 400, 7),       # 400 as a middle mode (tiles span several outer indices)
     (9, 150, 60),      # 150 and 60 as strided modes, ragged last tile
     (1, 60, 150),      # a mode of length 1
