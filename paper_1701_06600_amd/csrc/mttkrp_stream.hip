@@ -38,6 +38,12 @@ __host__ __device__ constexpr int stream_gw() {
          : (kStreamAccRegs / stream_acc_regs<T, CPLX, CT>() >= 4 ? 4 : kStreamAccRegs / stream_acc_regs<T, CPLX, CT>());
 }
 
+// complex64 at R <= 16 runs held to four waves per SIMD (the _o4 kernel below)
+template <typename T, bool CPLX, int CT>
+constexpr bool stream_o4() {
+    return CPLX && sizeof(T) == 4 && CT <= 2;
+}
+
 template <typename T, bool CPLX, int CT, bool WEIGHTED>
 __device__ __forceinline__ void gather_stream_body(const KArgs &a) {
     typedef Geo<T, CPLX> G;
@@ -45,6 +51,10 @@ __device__ __forceinline__ void gather_stream_body(const KArgs &a) {
     constexpr int GW = stream_gw<T, CPLX, CT>();
     static_assert(GW >= 1, "accumulators exceed the register budget");
     constexpr int KS = kStreamLoads / GW;
+    // each chunk's first fiber batch issued before its Khatri-Rao rows; its
+    // registers stay live through them, which the four-wave complex64 form
+    // cannot hold without spilling
+    constexpr bool PRE = !stream_o4<T, CPLX, CT>();
     constexpr int LDB = ldb_for(CT, (int)sizeof(T));
     extern __shared__ __align__(16) unsigned char lds[];
 
@@ -116,8 +126,7 @@ __device__ __forceinline__ void gather_stream_body(const KArgs &a) {
     // MFMA output row depends only on its own A row, and those rows are never
     // stored.  The plan guarantees I_n % VE == 0, so a row in the block
     // starts a whole vector.
-    auto run_chunk = [&](const int ns) {
-        for (int ks = 0; ks < ns; ks += 4 * KS) {
+    auto load_batch = [&](const int ks, const int ns) {
 #pragma unroll
             for (int k = 0; k < KS; ++k) {
                 const int sl = ks + 4 * k + lk;
@@ -139,6 +148,12 @@ __device__ __forceinline__ void gather_stream_body(const KArgs &a) {
                     }
                 }
             }
+    };
+    // first: the chunk's first batch was issued before its Khatri-Rao rows
+    auto run_chunk = [&](const int ns, bool first) {
+        for (int ks = 0; ks < ns; ks += 4 * KS) {
+            if (!first) load_batch(ks, ns);
+            first = false;
             // keep the scheduler from sinking the loads toward their MFMAs
             // (which would leave two in flight): all are issued first
             __builtin_amdgcn_sched_barrier(0);
@@ -212,6 +227,10 @@ __device__ __forceinline__ void gather_stream_body(const KArgs &a) {
         }
         __syncthreads();
         fetch(c0 + KC, tc);
+        // the chunk's first fiber batch goes out now: under a loaded memory
+        // system the Khatri-Rao loads below take microseconds, and the
+        // workgroup keeps streaming through them
+        if (PRE && gw > 0) load_batch(0, ns);
         // mode by mode, four elements per pass (the accumulators stay live)
         chunk_krp_by_mode<T, CPLX, WEIGHTED, 4, true>(a, ns, LDZ, s_idx, s_w, Bre, nullptr, Zr, tc);
         if (ns < KC) {
@@ -240,7 +259,7 @@ __device__ __forceinline__ void gather_stream_body(const KArgs &a) {
                 }
             }
         }
-        if (gw > 0) run_chunk(ns);
+        if (gw > 0) run_chunk(ns, PRE);
         __syncthreads();  // the next chunk rewrites the LDS tiles
     }
 
@@ -301,12 +320,6 @@ __global__ __launch_bounds__(256) void gather_stream(KArgs a) {
 template <typename T, bool CPLX, int CT, bool WEIGHTED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gather_stream_o4(KArgs a) {
     gather_stream_body<T, CPLX, CT, WEIGHTED>(a);
-}
-
-// the form a launch uses
-template <typename T, bool CPLX, int CT>
-constexpr bool stream_o4() {
-    return CPLX && sizeof(T) == 4 && CT <= 2;
 }
 
 template <typename T, bool CPLX, int CT, bool WEIGHTED>
