@@ -17,10 +17,12 @@ namespace cprand {
 // consecutive rows (GW * 256 bytes) of each of its fibers per batch, runs of
 // fiber bytes long enough for full HBM efficiency under random fiber
 // addresses.  The split is processed in chunks of KC samples (indices and
-// Khatri-Rao rows in LDS); the other resident workgroups keep HBM busy while
-// one forms the rows of its next chunk.  The Gram of the split is accumulated by FP64
-// MFMA, one 16 x 16 output tile per wave (R <= 32), in row block 0.  The
-// samples always come drawn (idx); there is no in-kernel draw here.
+// Khatri-Rao rows in LDS); a chunk's first fiber batch is issued before its
+// Khatri-Rao loads, and the other resident workgroups keep HBM busy while
+// one forms the rows of its next chunk.  The Gram of the split is
+// accumulated by FP64 MFMA in row block 0 (R <= 16: the one 16 x 16 tile,
+// the k-steps dealt to the four waves; up to R = 32: three tiles, one per
+// wave).  The samples always come drawn (idx); there is no in-kernel draw.
 
 // accumulator registers of one row group
 template <typename T, bool CPLX, int CT>
@@ -28,9 +30,10 @@ __host__ __device__ constexpr int stream_acc_regs() {
     return CT * Geo<T, CPLX>::VE * (sizeof(T) == 8 ? 8 : 4);
 }
 // Row groups per wave: kStreamAccRegs accumulator registers at most, four
-// at most.  The budget sets the occupancy: the bytes a CU keeps in flight
-// (waves x 8 loads x 16 bytes x 64 lanes) bound the rate, and at 32
-// accumulator registers four waves per SIMD fit.
+// at most.  The budget bounds the occupancy: the bytes a CU keeps in flight
+// (waves x 8 loads x 16 bytes x 64 lanes) bound the rate.  With a chunk's
+// first batch held through its Khatri-Rao phase (below) the real kinds run
+// three waves per SIMD, which measured faster than four without it.
 constexpr int kStreamAccRegs = 32;
 template <typename T, bool CPLX, int CT>
 __host__ __device__ constexpr int stream_gw() {
