@@ -200,15 +200,25 @@ __global__ __launch_bounds__(NT) void dct_pass_pipe(const float *X, float *Y, in
     __shared__ int64_t cin[3][FIRST ? FC : 1];
     __shared__ float csign[3][FIRST ? FC : 1];
     __shared__ float lsign[FIRST ? L : 1];
+    // FIRST: every sign vector staged in LDS once (when they fit), so the
+    // per-tile sign products read no global memory
+    constexpr int kSignLds = 2048;
+    __shared__ int8_t sgl[FIRST ? kSignLds : 1];
     const int tid = threadIdx.x;
     const int64_t ncols = J * K;
     const int64_t ntiles = ceil_div(ncols, FC);
     const bool small = ncols < (int64_t)INT32_MAX;
+    int nsg = 0;
+    for (int mm = 0; mm < xi.order; ++mm) nsg += (int)xi.dims[mm];
     for (int e = tid; e < L; e += NT) {
         tw[e] = twg[e];
         cs[e] = csg[e];
         if (FIRST) lsign[e] = (float)signs[e];
     }
+    if (FIRST && nsg <= kSignLds)
+        for (int e = tid; e < nsg; e += NT) sgl[e] = signs[e];
+    const int8_t *sgp = (FIRST && nsg <= kSignLds) ? sgl : signs;
+    __syncthreads();  // the staged signs are read by the first tile's offsets below
     auto tile_info = [&](int64_t t, int slot) {
         for (int c = tid; c < FC; c += NT) {
             const int64_t q = t * FC + c;
@@ -238,7 +248,7 @@ __global__ __launch_bounds__(NT) void dct_pass_pipe(const float *X, float *Y, in
                         const uint32_t im = r % d;
                         r /= d;
                         off += (int64_t)im * xi.strides[mm];
-                        sg *= (float)signs[soff + (int)im];
+                        sg *= (float)sgp[soff + (int)im];
                         soff += (int)d;
                     }
                 } else {
@@ -247,7 +257,7 @@ __global__ __launch_bounds__(NT) void dct_pass_pipe(const float *X, float *Y, in
                         const int64_t im = r % xi.dims[mm];
                         r /= xi.dims[mm];
                         off += im * xi.strides[mm];
-                        sg *= (float)signs[soff + im];
+                        sg *= (float)sgp[soff + im];
                         soff += (int)xi.dims[mm];
                     }
                 }

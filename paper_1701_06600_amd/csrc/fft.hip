@@ -207,6 +207,7 @@ __global__ __launch_bounds__(NT) void mix_pass_pipe(const float *X, cx<float> *X
             for (int e = tid; e < nsg; e += NT) sgl[e] = signs[e];
     }
     const int8_t *sgp = (FIRST && nsg <= kSignLds) ? sgl : signs;
+    __syncthreads();  // the staged signs are read by the first tile's offsets below
     // 32-bit index arithmetic when the fiber count fits
     const bool small = ncols < (int64_t)INT32_MAX;
     // fiber offsets (and FIRST: sign products over the other modes) of tile t
