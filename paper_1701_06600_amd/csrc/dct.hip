@@ -480,6 +480,9 @@ hipError_t launch_dct_pass(const ModeInfo &xi, const void *X, int xkind, void *Y
         case 400:
             if (launch_dct_pipe<400, 16, 1024>(fp, tab, xi, X, Y, first, signs, J, K, st, &e, first ? ex : nullptr)) return e;
             return launch_dct_tiles<float, float, 400, 16, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
+        case 1000:  // 8 column pairs: the tile and its tables take ~95 KB of LDS
+            if (launch_dct_pipe<1000, 8, 512>(fp, tab, xi, X, Y, first, signs, J, K, st, &e, first ? ex : nullptr)) return e;
+            return launch_dct_tiles<float, float, 1000, 8, 512>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
         default: return launch_dct_generic<float, float>(fp, tab, xi, X, Y, m, first, signs, J, K, st);
     }
 }

@@ -25,6 +25,9 @@ SHAPES = [
     (400, 20, 3),      # compile-time 400, first pass
     (60, 7, 5),        # compile-time 60 and 150 first passes (norm folded in), ragged last tile
     (150, 6, 6),
+    (1000, 4, 5),      # compile-time 1000: first pass, one ragged tile
+    (4, 1000, 3),      # 1000 as a strided pipelined pass (J = 4)
+    (3, 1000, 2),      # 1000 as a strided pass the tiled kernel takes (J = 3)
     (3, 400, 7),       # 400 as a middle mode (tiles span several outer indices)
     (9, 150, 60),      # 150 and 60 as strided modes, ragged last tile
     (1, 60, 150),      # a mode of length 1
