@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 
 P = pytest.importorskip("paper_1701_06600_amd")
 
-CALLS = [  # (dims, n, R, S): a larger problem, then a smaller one
+CALLS = [  # (dims, n, R, S): each problem smaller than the one before
+    ((1000, 40, 30), 0, 10, 6000),  # S >= 4096: the streaming forms (FP32, FP64, BF16)
     ((300, 41, 52), 0, 16, 2000),
     ((60, 33, 20), 1, 5, 150),
 ]
