@@ -83,6 +83,23 @@ __global__ __launch_bounds__(256) void gather_contract_bf16(BfArgs a) {
     for (int e = tid; e < 16 * CT * ldz; e += blockDim.x) Zt[e] = 0;
     __syncthreads();
 
+    // loader role: sample ls (0..31) of each 32-sample step, rows lg*8 ..
+    // lg*8+7 of the block.  The first kBfPre steps' fibers of the lanes whose
+    // 8 rows are one 16-byte load go out now, so that their latency overlaps
+    // the Khatri-Rao loads and the Gram instead of one round trip per step.
+    const int ls = tid >> 3, lg = tid & 7;
+    const int rb = blockIdx.x * kBfRows;
+    const int r0 = rb + lg * 8;
+    const bool vec = CONTIG && r0 + 8 <= a.In;  // uniform per 8 lanes
+    constexpr int kBfPre = 4;
+    uint4 pre[kBfPre];
+#pragma unroll
+    for (int j = 0; j < kBfPre; ++j) {
+        const int sl = j * kBfStep + ls;
+        pre[j] = uint4{0u, 0u, 0u, 0u};
+        if (vec && sl < ns) pre[j] = *(const uint4 *)(a.X + s_base[sl] + r0);
+    }
+
     // Z_S rounded to BF16; the B operand carries the weights
     for (int e = tid; e < ns * R; e += blockDim.x) {
         const int sl = e / R, r = e - sl * R;
@@ -111,44 +128,53 @@ __global__ __launch_bounds__(256) void gather_contract_bf16(BfArgs a) {
     }
 
     const int wv = tid >> 6, l = tid & 63, li = l & 15, lq = l >> 4;
-    const int rb = blockIdx.x * kBfRows;
     const int In = a.In;
     const int64_t sn = a.mi.strides[n];
-    // loader role: sample ls (0..31), rows lg*8 .. lg*8+7 of the block
-    const int ls = tid >> 3, lg = tid & 7;
     v4f acc[CT];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[ct] = v4f{0, 0, 0, 0};
 
-    for (int ks = 0; ks < ns; ks += kBfStep) {
-        uint16_t vals[8];
+    // steps in groups of kBfPre (unrolled, so the preloaded registers are
+    // indexed at compile time)
+    for (int ks0 = 0; ks0 < ns; ks0 += kBfPre * kBfStep) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) vals[e] = 0;
-        const int sl = ks + ls;
-        const int r0 = rb + lg * 8;
-        if (sl < ns && r0 < In) {
-            const int64_t b = s_base[sl];
-            if (CONTIG && r0 + 8 <= In) {
-                const uint4 q = *(const uint4 *)(a.X + b + r0);
+        for (int j = 0; j < kBfPre; ++j) {
+            const int ks = ks0 + j * kBfStep;
+            if (ks >= ns) break;  // uniform
+            uint16_t vals[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) vals[e] = 0;
+            const int sl = ks + ls;
+            if (ks0 == 0 && vec) {  // loaded above (zero past the chunk)
+                const uint4 q = pre[j];
                 vals[0] = q.x & 0xffff; vals[1] = q.x >> 16;
                 vals[2] = q.y & 0xffff; vals[3] = q.y >> 16;
                 vals[4] = q.z & 0xffff; vals[5] = q.z >> 16;
                 vals[6] = q.w & 0xffff; vals[7] = q.w >> 16;
-            } else {
+            } else if (sl < ns && r0 < In) {
+                const int64_t b = s_base[sl];
+                if (vec) {
+                    const uint4 q = *(const uint4 *)(a.X + b + r0);
+                    vals[0] = q.x & 0xffff; vals[1] = q.x >> 16;
+                    vals[2] = q.y & 0xffff; vals[3] = q.y >> 16;
+                    vals[4] = q.z & 0xffff; vals[5] = q.z >> 16;
+                    vals[6] = q.w & 0xffff; vals[7] = q.w >> 16;
+                } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    if (r0 + e < In) vals[e] = a.X[b + (int64_t)(r0 + e) * sn];
+                    for (int e = 0; e < 8; ++e)
+                        if (r0 + e < In) vals[e] = a.X[b + (int64_t)(r0 + e) * sn];
+                }
             }
-        }
-        __syncthreads();  // previous step's A tile fully consumed
+            __syncthreads();  // previous step's A tile fully consumed
 #pragma unroll
-        for (int e = 0; e < 8; ++e) At[(lg * 8 + e) * lda + ls] = vals[e];
-        __syncthreads();
-        const v8bf av = *(const v8bf *)(At + (wv * 16 + li) * lda + lq * 8);
+            for (int e = 0; e < 8; ++e) At[(lg * 8 + e) * lda + ls] = vals[e];
+            __syncthreads();
+            const v8bf av = *(const v8bf *)(At + (wv * 16 + li) * lda + lq * 8);
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-            const v8bf bv = *(const v8bf *)(Zt + (ct * 16 + li) * ldz + ks + lq * 8);
-            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ct], 0, 0, 0);
+            for (int ct = 0; ct < CT; ++ct) {
+                const v8bf bv = *(const v8bf *)(Zt + (ct * 16 + li) * ldz + ks + lq * 8);
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ct], 0, 0, 0);
+            }
         }
     }
 
