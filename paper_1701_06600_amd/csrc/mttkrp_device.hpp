@@ -63,11 +63,12 @@ struct KArgs {
 
 // Fiber values of one MFMA batch: lane (li, lk) takes sample ks + 4u + lk
 // (u < kUnroll) and rows row0 .. row0 + VE - 1 of its mode-n fiber.
-// fast (contiguous fibers, I_n % VE == 0): every load unconditional, no
-// branch between them, so all stay in flight together; a lane past the
-// chunk reads the chunk's last fiber (its B operand row is zero) and a row
-// past the fiber reads the fiber's last vector (output rows that are never
-// stored: each MFMA output row depends only on its own A row).
+// fast (contiguous fibers, I_n % VE == 0), and strided fibers: every load
+// unconditional, no branch between them, so all stay in flight together; a
+// lane past the chunk reads the chunk's last fiber (its B operand row is
+// zero) and a row past the fiber reads the fiber's last vector or element
+// (output rows that are never stored: each MFMA output row depends only on
+// its own A row).
 template <typename T, bool CPLX, bool CONTIG>
 __device__ __forceinline__ void load_fibers(T (&v)[kUnroll][16 / sizeof(T)], const T *xp, const int64_t *s_base,
                                             int ns, int ks, int row0, int lk, int In, int64_t sn, bool fast) {
@@ -90,6 +91,28 @@ __device__ __forceinline__ void load_fibers(T (&v)[kUnroll][16 / sizeof(T)], con
                 const double2 q = *(const double2 *)src;
                 v[u][0] = q.x;
                 v[u][1] = q.y;
+            }
+        }
+        return;
+    }
+    if (!CONTIG) {
+        // strided fibers: the same clamping, one load per element, all of
+        // them unconditional (a load behind a branch is waited for at the
+        // branch's end, which would serialize the batch)
+        int64_t b[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) b[u] = s_base[min(ks + 4 * u + lk, ns - 1)];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+#pragma unroll
+            for (int c = 0; c < G::VE; ++c) {
+                const int64_t o = b[u] + (int64_t)min(row0 + c, In - 1) * sn;
+                if (CPLX) {
+                    v[u][2 * c] = xp[2 * o];
+                    v[u][2 * c + 1] = xp[2 * o + 1];
+                } else {
+                    v[u][c] = xp[o];
+                }
             }
         }
         return;
