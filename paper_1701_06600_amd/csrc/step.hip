@@ -390,11 +390,42 @@ __global__ __launch_bounds__(kStepThreads) void step_finish_kernel(StepArgs a) {
         }
         return;
     }
-    for (int e = tid; e < In * R; e += kStepThreads) {
-        const int i = e / R, r = e - i * R;
-        double s = 0.0;
-        for (int k = 0; k < R; ++k) s += Wd[i * R + k] * B1[k * ld + r];
-        Ad[e] = s;
+    if (R <= 16) {
+        // A = W V^{-1} on FP64 MFMA 16x16x4 (as for the mixed solve), tiles
+        // of 16 rows dealt to the waves: lane (li, lk) feeds A(row li, k lk)
+        // = W(tile row li, 4c + lk) and B(k lk, col li) = V^{-1}(4c + lk, li)
+        // and holds rows lk + 4v of column li
+        const int wv = tid / kWave, l = tid & (kWave - 1), li = l & 15, lk = l >> 4;
+        constexpr int nw = kStepThreads / kWave;
+        double bo[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int jj = 4 * c + lk;
+            bo[c] = (jj < R && li < R) ? B1[jj * ld + li] : 0.0;
+        }
+        const int ntile = (In + 15) / 16;
+        for (int tile = wv; tile < ntile; tile += nw) {  // uniform per wave
+            const int i = tile * 16 + li;
+            v4d d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int jj = 4 * c + lk;
+                const double av = (i < In && jj < R) ? Wd[i * R + jj] : 0.0;
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bo[c], d, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int io = tile * 16 + lk + 4 * v;
+                if (io < In && li < R) Ad[io * R + li] = d[v];
+            }
+        }
+    } else {
+        for (int e = tid; e < In * R; e += kStepThreads) {
+            const int i = e / R, r = e - i * R;
+            double s = 0.0;
+            for (int k = 0; k < R; ++k) s += Wd[i * R + k] * B1[k * ld + r];
+            Ad[e] = s;
+        }
     }
     __syncthreads();
     if (a.Wref) {
